@@ -1,0 +1,373 @@
+"""FP64 CPU oracle: armchair graphene ribbon conductance by the recursive
+Green's function method.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring). Plain numpy, complex128,
+dense matrices, no structure tricks and no blocking beyond what the equations
+state. Nothing here is shared with the HIP library.
+
+Model (paper: model paragraph and Fig. 1(a); readings listed in the design doc):
+  * slice i = 1..L holds N atoms, one p orbital each, indexed k = 0..N-1 along
+    the transverse zigzag chain of an armchair ribbon;
+  * slice Hamiltonian H_i = diag(eps_i) + t * (k <-> k+1 path adjacency);
+  * slice i couples to slice i+1 through the diagonal block
+    U_i = t * diag([(k + i + parity) even]), so consecutive slices alternate
+    which half of the chain carries the longitudinal bonds;
+  * two semi-infinite pristine leads (eps = 0, same N, same parity rule) are
+    attached to slice 1 and slice L;
+  * z = E + i*eta is used in the leads and in the device alike.
+
+All energies and t, eta, eps are in eV; the conductance is in units of 2e^2/h.
+"""
+
+import numpy as np
+
+__all__ = [
+    "coupling_mask",
+    "slice_hamiltonian",
+    "coupling",
+    "sancho_rubio",
+    "lead_self_energies",
+    "transmission",
+    "transmission_rl",
+    "transmission_bf",
+    "transmission_grad",
+    "transmission_grad_bf",
+    "open_channels",
+    "half_gap",
+    "transmission_sweep",
+]
+
+
+# --------------------------------------------------------------------------
+# Model: the slice Hamiltonian and the inter-slice hopping (model paragraph;
+# Fig. 1(a): armchair edges, one p orbital per carbon atom).
+# --------------------------------------------------------------------------
+
+def coupling_mask(N, i, parity=0):
+    """Boolean vector: rows k of slice i that bond to slice i+1."""
+    k = np.arange(N)
+    return ((k + i + parity) % 2) == 0
+
+
+def slice_hamiltonian(N, t, eps_row=None):
+    """H_i = diag(eps) + t * path adjacency (the transverse zigzag chain)."""
+    H = np.zeros((N, N), dtype=np.complex128)
+    if eps_row is not None:
+        H[np.arange(N), np.arange(N)] = np.asarray(eps_row, dtype=np.float64)
+    for k in range(N - 1):
+        H[k, k + 1] = t
+        H[k + 1, k] = t
+    return H
+
+
+def coupling(N, t, i, parity=0):
+    """U_i = H_{i,i+1}: hopping block from slice i to slice i+1."""
+    return np.diag(np.where(coupling_mask(N, i, parity), t, 0.0)).astype(np.complex128)
+
+
+# --------------------------------------------------------------------------
+# Leads: surface Green's function by Sancho-Rubio decimation
+# (M. P. Lopez Sancho, J. M. Lopez Sancho, J. Rubio, J. Phys. F 15 (1985) 851).
+# The paper obtains the lead self-energies at slices 1 and M separately from
+# the recursion (method section); the decimation yields the same retarded
+# surface Green's function.
+# --------------------------------------------------------------------------
+
+def sancho_rubio(z, h00, h01, tol=1e-15, maxit=200):
+    """Surface Green's function of a semi-infinite stack of identical layers.
+
+    h00: Hamiltonian of one layer; h01: hopping from the surface layer to the
+    next layer deeper in the stack (the reverse hopping is h01^T since H is
+    real symmetric). Returns (g_surf, iterations, converged).
+    """
+    n = h00.shape[0]
+    eye = np.eye(n, dtype=np.complex128)
+    eps_s = h00.astype(np.complex128).copy()
+    eps_b = h00.astype(np.complex128).copy()
+    alpha = h01.astype(np.complex128).copy()
+    beta = h01.T.astype(np.complex128).copy()
+    scale = max(np.abs(h01).max(), np.abs(h00).max(), 1.0)
+    it = 0
+    converged = False
+    while it < maxit:
+        g = np.linalg.inv(z * eye - eps_b)
+        agb = alpha @ g @ beta
+        bga = beta @ g @ alpha
+        eps_s = eps_s + agb
+        eps_b = eps_b + agb + bga
+        alpha = alpha @ g @ alpha
+        beta = beta @ g @ beta
+        it += 1
+        if max(np.abs(alpha).max(), np.abs(beta).max()) < tol * scale:
+            converged = True
+            break
+    return np.linalg.inv(z * eye - eps_s), it, converged
+
+
+def _lead_cells(N, t, L, parity):
+    """Two-slice principal layers of the left and right leads.
+
+    Left lead: surface cell (slice -1, slice 0); the next cell deeper is
+    (slice -3, slice -2) and the only bond between them is slice -1 <-> -2.
+    Right lead: surface cell (slice L+1, slice L+2); next cell (L+3, L+4),
+    bonded through slice L+2 <-> L+3.
+    """
+    H0 = slice_hamiltonian(N, t)
+    Z = np.zeros((N, N), dtype=np.complex128)
+    # left
+    Um1 = coupling(N, t, -1, parity)
+    Um2 = coupling(N, t, -2, parity)
+    h00_l = np.block([[H0, Um1], [Um1.T, H0]])
+    h01_l = np.block([[Z, Um2.T], [Z, Z]])  # row: slice -1, column: slice -2
+    # right
+    Up1 = coupling(N, t, L + 1, parity)
+    Up2 = coupling(N, t, L + 2, parity)
+    h00_r = np.block([[H0, Up1], [Up1.T, H0]])
+    h01_r = np.block([[Z, Z], [Up2, Z]])  # row: slice L+2, column: slice L+3
+    return (h00_l, h01_l), (h00_r, h01_r)
+
+
+def lead_self_energies(N, L, t, eta, E, parity=0, tol=1e-15, maxit=200,
+                       return_info=False):
+    """Sigma_L (acts on slice 1) and Sigma_R (acts on slice L), N x N each.
+
+    Sigma_L = H_{1,0} g_L H_{0,1} = U_0^T g_L[0,0] U_0,
+    Sigma_R = H_{L,L+1} g_R H_{L+1,L} = U_L g_R[L+1,L+1] U_L^T.
+    """
+    z = complex(E, eta)
+    (h00_l, h01_l), (h00_r, h01_r) = _lead_cells(N, t, L, parity)
+    gl, itl, okl = sancho_rubio(z, h00_l, h01_l, tol, maxit)
+    gr, itr, okr = sancho_rubio(z, h00_r, h01_r, tol, maxit)
+    g0 = gl[N:, N:]        # slice 0 block of the left surface cell
+    gLp1 = gr[:N, :N]      # slice L+1 block of the right surface cell
+    U0 = coupling(N, t, 0, parity)
+    UL = coupling(N, t, L, parity)
+    sig_l = U0.T @ g0 @ U0
+    sig_r = UL @ gLp1 @ UL.T
+    if not return_info:
+        return sig_l, sig_r
+    info = {
+        "iterations": (itl, itr),
+        "converged": (okl, okr),
+        "g_surf": (gl, gr),
+        "cells": ((h00_l, h01_l), (h00_r, h01_r)),
+    }
+    return sig_l, sig_r, info
+
+
+def _gamma(sig):
+    """Broadening Gamma = i (Sigma - Sigma^dagger) (Eq. (2) and its reference)."""
+    return 1j * (sig - sig.conj().T)
+
+
+# --------------------------------------------------------------------------
+# Recursive Green's function (Eqs. (3)-(5)).
+#
+# Eq. (4) is used in its algebraically identical form
+#   g_jj = (E - H_j - Sigma^l g_{j-1,j-1} Sigma^r)^{-1},
+# with Sigma^l = H_{j,j-1} = U_{j-1}^T and Sigma^r = H_{j-1,j} = U_{j-1} the
+# inter-slice hopping blocks, and Eq. (5) as the running product
+#   G_{1j} = G_{1,j-1} Sigma^r g_jj.
+# The lead self-energies enter at the first and the last slice; after the last
+# slice G_{1L} is the block of the full Green's function of Eq. (1) that
+# Eq. (2) needs.
+# --------------------------------------------------------------------------
+
+def _device_slices(N, L, t, eps):
+    if eps is None:
+        eps = np.zeros((L, N))
+    eps = np.asarray(eps, dtype=np.float64)
+    assert eps.shape == (L, N)
+    return [slice_hamiltonian(N, t, eps[i]) for i in range(L)]
+
+
+def transmission(N, L, t, eta, E, eps=None, parity=0, sigmas=None,
+                 return_g=False):
+    """T(E) = Re Tr[Gamma_L G_1L Gamma_R G_1L^dagger] by the left-to-right sweep."""
+    z = complex(E, eta)
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    sig_l, sig_r = sigmas
+    Hs = _device_slices(N, L, t, eps)
+    eye = np.eye(N, dtype=np.complex128)
+    # slice 1
+    A = z * eye - Hs[0] - sig_l
+    if L == 1:
+        A = A - sig_r
+    g = np.linalg.inv(A)
+    G1 = g
+    for j in range(2, L + 1):
+        U = coupling(N, t, j - 1, parity)          # H_{j-1,j}
+        A = z * eye - Hs[j - 1] - U.T @ g @ U
+        if j == L:
+            A = A - sig_r
+        g = np.linalg.inv(A)
+        G1 = G1 @ U @ g
+    T = np.real(np.trace(_gamma(sig_l) @ G1 @ _gamma(sig_r) @ G1.conj().T))
+    if return_g:
+        return T, G1
+    return T
+
+
+def transmission_rl(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
+    """T_RL = Re Tr[Gamma_R G_L1 Gamma_L G_L1^dagger] by the right-to-left sweep.
+
+    Same Dyson recursion run from slice L down to slice 1; equals T_LR for a
+    two-terminal system (self-check).
+    """
+    z = complex(E, eta)
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    sig_l, sig_r = sigmas
+    Hs = _device_slices(N, L, t, eps)
+    eye = np.eye(N, dtype=np.complex128)
+    A = z * eye - Hs[L - 1] - sig_r
+    if L == 1:
+        A = A - sig_l
+    g = np.linalg.inv(A)
+    GL = g                                       # G_{L,j} (right-connected)
+    for j in range(L - 1, 0, -1):
+        U = coupling(N, t, j, parity)            # H_{j,j+1}
+        A = z * eye - Hs[j - 1] - U @ g @ U.T
+        if j == 1:
+            A = A - sig_l
+        g = np.linalg.inv(A)
+        GL = GL @ U.T @ g
+    return np.real(np.trace(_gamma(sig_r) @ GL @ _gamma(sig_l) @ GL.conj().T))
+
+
+def _full_matrix(N, L, t, eta, E, eps, parity, sigmas):
+    """z - H - Sigma_L - Sigma_R over all N*L device sites (Eq. (1))."""
+    z = complex(E, eta)
+    Hs = _device_slices(N, L, t, eps)
+    M = np.zeros((N * L, N * L), dtype=np.complex128)
+    for i in range(L):
+        M[i * N:(i + 1) * N, i * N:(i + 1) * N] = z * np.eye(N) - Hs[i]
+        if i + 1 < L:
+            U = coupling(N, t, i + 1, parity)
+            M[i * N:(i + 1) * N, (i + 1) * N:(i + 2) * N] = -U
+            M[(i + 1) * N:(i + 2) * N, i * N:(i + 1) * N] = -U.T
+    sig_l, sig_r = sigmas
+    M[:N, :N] -= sig_l
+    M[(L - 1) * N:, (L - 1) * N:] -= sig_r
+    return M
+
+
+def transmission_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
+    """Brute force: invert the full device matrix, then Eq. (2)."""
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    sig_l, sig_r = sigmas
+    G = np.linalg.inv(_full_matrix(N, L, t, eta, E, eps, parity, sigmas))
+    G1L = G[:N, (L - 1) * N:]
+    return np.real(np.trace(_gamma(sig_l) @ G1L @ _gamma(sig_r) @ G1L.conj().T))
+
+
+# --------------------------------------------------------------------------
+# Gradient dT/d eps_{i,k}.
+#
+# From Eq. (1): dG/d eps_s = G E_ss G, so Eq. (2) gives
+#   dT/d eps_s = 2 Re[ G[s, slice L] B G[slice 1, s] ],  B = Gamma_R G_1L^dag Gamma_L.
+# --------------------------------------------------------------------------
+
+def transmission_grad_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
+    """(T, dT/deps [L, N]) from the full inverse (tiny ribbons only)."""
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    sig_l, sig_r = sigmas
+    G = np.linalg.inv(_full_matrix(N, L, t, eta, E, eps, parity, sigmas))
+    G1L = G[:N, (L - 1) * N:]
+    gl, gr = _gamma(sig_l), _gamma(sig_r)
+    T = np.real(np.trace(gl @ G1L @ gr @ G1L.conj().T))
+    B = gr @ G1L.conj().T @ gl
+    right = G[:, (L - 1) * N:]       # G[s, slice L]
+    left = G[:N, :]                  # G[slice 1, s]
+    d = 2.0 * np.real(np.einsum("sa,ab,bs->s", right, B, left))
+    return T, d.reshape(L, N)
+
+
+def transmission_grad(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
+    """(T, dT/deps [L, N]) by a forward and a backward Dyson sweep.
+
+    Forward (left-connected, Eq. (4)-(5) form): g_i, the running
+    G1_i = g_{1,i} and the column block g_{i,1}.
+    Backward (Eq. (3) with the cut between slices i and i+1, both orders):
+      F_{i,L} = g_i U_i F_{i+1,L},          F_{L,L} = g_L
+      F_{i,1} = g_{i,1} + g_i U_i F_{i+1,1}, F_{L,1} = g_{L,1}
+      F_{1,i} = G1_i + F_{1,i+1} U_i^T g_i, F_{1,L} = G1_L
+    where F is the full-system Green's function.
+    """
+    z = complex(E, eta)
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    sig_l, sig_r = sigmas
+    Hs = _device_slices(N, L, t, eps)
+    eye = np.eye(N, dtype=np.complex128)
+    gs, G1s = [], []
+    A = z * eye - Hs[0] - sig_l
+    if L == 1:
+        A = A - sig_r
+    g = np.linalg.inv(A)
+    gs.append(g)
+    G1s.append(g)
+    for j in range(2, L + 1):
+        U = coupling(N, t, j - 1, parity)
+        A = z * eye - Hs[j - 1] - U.T @ g @ U
+        if j == L:
+            A = A - sig_r
+        g = np.linalg.inv(A)
+        gs.append(g)
+        G1s.append(G1s[-1] @ U @ g)
+    G1L = G1s[-1]
+    gl, gr = _gamma(sig_l), _gamma(sig_r)
+    T = np.real(np.trace(gl @ G1L @ gr @ G1L.conj().T))
+    B = gr @ G1L.conj().T @ gl
+    d = np.zeros((L, N))
+    FiL = gs[-1]                    # F_{L,L}
+    F1i = G1L                       # F_{1,L}
+    d[L - 1] = 2.0 * np.real(np.einsum("ka,ab,bk->k", FiL, B, F1i))
+    for i in range(L - 1, 0, -1):   # slice i (1-based), python index i-1
+        U = coupling(N, t, i, parity)
+        FiL = gs[i - 1] @ U @ FiL
+        F1i = G1s[i - 1] + F1i @ U.T @ gs[i - 1]
+        d[i - 1] = 2.0 * np.real(np.einsum("ka,ab,bk->k", FiL, B, F1i))
+    return T, d
+
+
+# --------------------------------------------------------------------------
+# Closed forms for the pristine armchair ribbon.
+# --------------------------------------------------------------------------
+
+def open_channels(N, E, t):
+    """Number of propagating channels M(E) in the pristine lead.
+
+    Transverse modes p and N+1-p of the zigzag chain pair up; each pair is a
+    chain with alternating hoppings |t| and 2|t|cos(p pi/(N+1)), whose band
+    covers |1 - 2c_p| < |E|/|t| < 1 + 2c_p and carries one right-moving state.
+    A metallic ribbon (N = 2 mod 3) has one channel at E = 0.
+    """
+    x = abs(E) / abs(t)
+    p = np.arange(1, N // 2 + 1)
+    c = np.cos(p * np.pi / (N + 1))
+    m = int(np.sum((np.abs(1.0 - 2.0 * c) < x) & (x < 1.0 + 2.0 * c)))
+    if x == 0.0 and N % 3 == 2:
+        m += 1
+    return m
+
+
+def half_gap(N, t):
+    """Half of the band gap around E = 0 of the pristine ribbon, in eV."""
+    p = np.arange(1, N // 2 + 1)
+    return abs(t) * float(np.min(np.abs(1.0 - 2.0 * np.cos(p * np.pi / (N + 1)))))
+
+
+# --------------------------------------------------------------------------
+# Convenience: an energy sweep sharing the lead self-energies per energy.
+# --------------------------------------------------------------------------
+
+def transmission_sweep(N, L, t, eta, energies, eps=None, parity=0):
+    """T for each energy (one realization), by transmission()."""
+    out = np.empty(len(energies))
+    for j, E in enumerate(energies):
+        out[j] = transmission(N, L, t, eta, float(E), eps, parity)
+    return out
