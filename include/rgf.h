@@ -1,0 +1,164 @@
+/*
+ * rgf.h -- C ABI of librgf: recursive Green's function (RGF) conductance of
+ * armchair graphene nanoribbons on AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Ihnatsenka, Comput. Phys. Commun. 183 (2012) 543
+ * (arXiv:1107.5300). Eq. (1) defines the retarded Green's function
+ * G = (E - H)^{-1} of the ribbon with both leads folded in as self-energies;
+ * Eq. (2) the two-terminal conductance G = (2e^2/h) Tr[Gamma_L G^a Gamma_R G^r];
+ * Eqs. (3)-(5) the slice-by-slice Dyson recursion that produces the block of
+ * G between the first and the last slice; the method section obtains the
+ * lead self-energies at the first and last slice separately (here: Sancho-
+ * Rubio decimation, in FP64).
+ *
+ * Model (model paragraph, Fig. 1(a)): N atoms per transverse slice (one p
+ * orbital each) along a zigzag chain, L slices, nearest-neighbour hopping t.
+ * Slice i (1..L) couples to slice i+1 through the rows k = 0..N-1 with
+ * (k + i + parity) even. On-site energies eps[r][i][k] describe disorder
+ * realization r; the two semi-infinite leads are pristine ribbons of the same
+ * width. z = E + i*eta is used in the leads and in the device.
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers to float64 data (complex values
+ *     never cross the boundary, except the debug export of the lead
+ *     self-energies, which is interleaved (re, im) float64), in row-major
+ *     C order, owned by the caller. The library allocates no device memory on
+ *     any path: scratch space is the caller's workspace.
+ *   - Calls are asynchronous on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL = the null stream). The return value reports only errors
+ *     found before anything is enqueued (invalid arguments, an undersized
+ *     workspace, a width the kernels do not support) or a failed launch; on
+ *     such an error nothing is written.
+ *   - Numerical failures of a (realization, energy) tuple are reported per
+ *     tuple in status_out (RGF_TUPLE_*), with T = NaN, without a host sync.
+ *   - Energies, t, eta and eps are in eV; conductances in units of 2e^2/h;
+ *     gradients in (2e^2/h)/eV.
+ *   - Not thread-safe per stream: concurrent calls on one stream are ordered
+ *     by the stream; calls on different streams must use different
+ *     workspaces.
+ */
+#ifndef RGF_H
+#define RGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RGF_ABI_VERSION_MAJOR 1
+#define RGF_ABI_VERSION_MINOR 0
+
+/* Ribbon geometry and model constants. */
+typedef struct {
+  uint32_t struct_size; /* = sizeof(rgf_ribbon_desc), for versioning        */
+  int32_t width_n;      /* N atoms per transverse slice, 2..RGF_MAX_WIDTH    */
+  int32_t length_l;     /* L slices in the scattering region, >= 1          */
+  int32_t parity;       /* 0 or 1: slice i bonds rows (k + i + parity) even */
+  double hopping_ev;    /* t, finite and != 0 (e.g. -2.7)                    */
+  double eta_ev;        /* eta > 0 and finite (e.g. 1e-8)                     */
+} rgf_ribbon_desc;
+
+#define RGF_MAX_WIDTH 256
+
+/* Arithmetic of the slice recursion. The lead self-energies, the running
+ * propagator G_1i and the trace are FP64 in every mode. */
+enum {
+  RGF_PREC_FP64 = 0,  /* complex128 throughout                                  */
+  RGF_PREC_MIXED = 1, /* complex64 slice inversions + FP64 residual refinement  */
+  RGF_PREC_FP32 = 2   /* complex64 slice inversions, no refinement (accuracy
+                         study of single precision; not for production)       */
+};
+
+enum {
+  RGF_OK = 0,
+  RGF_ERR_INVALID_ARG = -1,
+  RGF_ERR_HIP = -2,
+  RGF_ERR_WORKSPACE = -3,
+  RGF_ERR_UNSUPPORTED = -4
+};
+
+enum {
+  RGF_TUPLE_OK = 0,
+  RGF_TUPLE_NO_CONVERGENCE = 1, /* lead decimation hit its iteration cap     */
+  RGF_TUPLE_SINGULAR = 2,       /* exact zero pivot in a slice inversion     */
+  RGF_TUPLE_NONFINITE = 3       /* T came out NaN or Inf                     */
+};
+
+/* Bytes of device workspace the call with the same arguments needs.
+ * want_grad != 0 sizes it for rgf_grad with checkpoint stride ckpt_stride
+ * (0 = automatic). Returns 0 for invalid arguments (see rgf_last_error_message). */
+size_t rgf_workspace_bytes(const rgf_ribbon_desc* desc, int64_t n_energies,
+                           int64_t n_real, int precision, int want_grad,
+                           int64_t ckpt_stride);
+
+/* Conductance T[r][e] (Eq. (2)) for every realization r and energy e.
+ *   energies_ev   [n_energies]
+ *   onsite_eps_ev [n_real][L][N], or NULL for pristine ribbons (then n_real
+ *                 is the number of identical output rows)
+ *   T_out         [n_real][n_energies]
+ *   status_out    [n_real][n_energies] int32, or NULL
+ * The recursion follows Eqs. (4)-(5); the lead self-energies (method
+ * section) are computed once per energy and shared by all realizations. */
+int rgf_conductance(const rgf_ribbon_desc* desc, const double* energies_ev,
+                    int64_t n_energies, const double* onsite_eps_ev,
+                    int64_t n_real, int precision, double* T_out,
+                    int32_t* status_out, void* workspace,
+                    size_t workspace_bytes, void* hip_stream);
+
+/* Conductance and the gradient of L = sum_{r,e} dL_dT[r][e] * T[r][e] with
+ * respect to every on-site energy (vector-Jacobian product of Eq. (2)
+ * through Eqs. (1), (4), (5)):
+ *   dL_deps[r][i][k] = sum_e dL_dT[r][e] * dT[r][e] / d eps[r][i][k].
+ * dL_deps is overwritten. ckpt_stride: half-slices between stored restart
+ * states of the forward sweep (0 = automatic, about sqrt(2L)); memory for
+ * the backward sweep is O((2L/ckpt_stride + ckpt_stride) N^2) per tuple. */
+int rgf_grad(const rgf_ribbon_desc* desc, const double* energies_ev,
+             int64_t n_energies, const double* onsite_eps_ev, int64_t n_real,
+             int precision, const double* dL_dT, double* T_out,
+             double* dL_deps, int64_t ckpt_stride, int32_t* status_out,
+             void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Several ribbons of different widths in one call (energy sweeps x disorder
+ * realizations x widths). Ribbon d uses descs[d], its on-site energies at
+ * onsite_eps_ev + eps_offsets[d] ([n_real][L_d][N_d]) and writes
+ * T_out + T_offsets[d] ([n_real][n_energies]) and the same offset into
+ * status_out (may be NULL). All ribbons share energies_ev, n_real and
+ * precision. Work is ordered largest width first. */
+size_t rgf_batched_workspace_bytes(const rgf_ribbon_desc* descs, int32_t n_desc,
+                                   int64_t n_energies, int64_t n_real,
+                                   int precision);
+int rgf_conductance_batched(const rgf_ribbon_desc* descs, int32_t n_desc,
+                            const int64_t* eps_offsets,
+                            const int64_t* T_offsets,
+                            const double* energies_ev, int64_t n_energies,
+                            const double* onsite_eps_ev, int64_t n_real,
+                            int precision, double* T_out, int32_t* status_out,
+                            void* workspace, size_t workspace_bytes,
+                            void* hip_stream);
+
+/* Lead self-energies (method section; Sancho-Rubio decimation in FP64),
+ * restricted to the rows that bond to the device:
+ *   sigma_l_out [n_energies][nl][nl][2]  on slice-1 rows (k + parity) even,
+ *   sigma_r_out [n_energies][nr][nr][2]  on slice-L rows (k + L + parity) even,
+ * with nl, nr the sizes of those row sets (returned through nl_out, nr_out;
+ * pass NULL outputs to query the sizes only). Interleaved (re, im) float64.
+ * lead_status_out [n_energies] int32 (RGF_TUPLE_*), or NULL. */
+int rgf_lead_self_energy(const rgf_ribbon_desc* desc, const double* energies_ev,
+                         int64_t n_energies, double* sigma_l_out,
+                         double* sigma_r_out, int32_t* lead_status_out,
+                         int32_t* nl_out, int32_t* nr_out, void* workspace,
+                         size_t workspace_bytes, void* hip_stream);
+
+/* Static descriptions. rgf_last_error_message is thread-local and describes
+ * the last non-OK return of this thread. */
+const char* rgf_status_string(int status);
+const char* rgf_last_error_message(void);
+int rgf_version(int* major, int* minor);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGF_H */

@@ -1,0 +1,68 @@
+// rgf_internal.hpp -- host-side plan shared by the C ABI and the launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rgf.h"
+
+namespace rgf {
+
+// Register tiling of one workgroup: NW waves; lane l owns rows l + 64 s
+// (s < S) and wave w owns columns w*C .. w*C + C - 1 of every n x n matrix
+// of the half-slice recursion, padded to NP = NW*C with the identity.
+struct TileCfg {
+  int id;  // index into the kernel table of a launcher
+  int NW, S, C;
+  int NP() const { return NW * C; }
+  int threads() const { return NW * 64; }
+};
+
+// Pick the smallest register tiling whose padded size NP holds n rows.
+// Returns false if n exceeds the largest tiling.
+bool pick_tile(int n, int precision, TileCfg* out);
+
+// Number of transverse modes of the lead (mode pairs plus the middle mode of
+// odd N).
+inline int lead_modes(int N) { return (N + 1) / 2; }
+
+// Byte layout of one call's workspace.
+struct Plan {
+  int N, L, parity, P, n1, nmax;
+  double t, eta;
+  int64_t nE, nreal, ntuples;
+  int precision;
+  TileCfg tile;
+  int grid;           // persistent workgroups
+  int64_t slot_elems; // complex elements of one matrix buffer (NP*NP)
+  int slot_mats;      // matrix buffers per slot
+  // byte offsets
+  size_t off_sigma, off_phi, off_lstat, off_status, off_slots, off_ckpt, off_seg,
+      total;
+  int64_t ckpt_stride, n_ckpt;
+  bool want_grad;
+};
+
+// Fill the plan; returns RGF_OK or an error code (with message set).
+int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision,
+              int want_grad, int64_t ckpt_stride, Plan* p);
+
+void set_error(const char* fmt, ...);
+
+// Launchers (enqueue only; return hipError_t).
+hipError_t launch_lead(const Plan& p, const double* E, char* ws, hipStream_t s);
+hipError_t launch_forward(const Plan& p, const double* E, const double* eps,
+                          double* T_out, int32_t* status_out, char* ws,
+                          hipStream_t s);
+hipError_t launch_export_sigma(const Plan& p, const double* E, double* sl,
+                               double* sr, int32_t* lstat_out, char* ws,
+                               hipStream_t s);
+hipError_t launch_grad(const Plan& p, const double* E, const double* eps,
+                       const double* dL_dT, double* T_out, double* dL_deps,
+                       int32_t* status_out, char* ws, hipStream_t s);
+
+// Persistent grid size for a tile config on the current device.
+int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad);
+
+}  // namespace rgf

@@ -1,0 +1,147 @@
+"""Python/torch binding of librgf (argument marshalling only).
+
+Every numeric step runs in the HIP kernels of librgf.so; torch provides
+device memory (the call's workspace and outputs) and the stream. Inputs must
+be float64 tensors on the current CUDA (HIP) device.
+"""
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as _L
+
+PRECISIONS = {"fp64": _L.RGF_PREC_FP64, "mixed": _L.RGF_PREC_MIXED, "fp32": _L.RGF_PREC_FP32}
+
+
+@dataclass(frozen=True)
+class Ribbon:
+    """Armchair ribbon: N atoms per slice, L slices, hopping t and broadening
+    eta in eV; slice i bonds rows (k + i + parity) even to slice i+1."""
+    N: int
+    L: int
+    parity: int = 0
+    t: float = -2.7
+    eta: float = 1e-8
+
+    def desc(self):
+        return _L.make_desc(self.N, self.L, self.parity, self.t, self.eta)
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _vp(x):
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(x, name, shape=None):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if x.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(shape)}")
+
+
+class Workspace:
+    """Device scratch for librgf calls, grown on demand (torch allocator)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _workspace(ws, nbytes, device):
+    if ws is None:
+        ws = _default_ws.setdefault(device.index, Workspace())
+    return ws.get(nbytes, device)
+
+
+def workspace_bytes(ribbon, n_energies, n_real=1, precision="fp64", want_grad=False,
+                    ckpt_stride=0):
+    d = ribbon.desc()
+    n = _L.lib().rgf_workspace_bytes(ctypes.byref(d), int(n_energies), int(n_real),
+                                     _prec(precision), int(bool(want_grad)), int(ckpt_stride))
+    if n == 0:
+        msg = _L.lib().rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    return n
+
+
+def conductance(ribbon, energies, eps=None, n_real=1, precision="fp64", workspace=None,
+                return_status=False, out=None):
+    """T[r, e] in units of 2e^2/h (Eq. (2) of the paper) for each disorder
+    realization r (eps[r] of shape [L, N], or pristine if eps is None) and
+    energy e. Asynchronous on the current stream."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    if eps is not None:
+        if eps.dim() == 2:
+            eps = eps.unsqueeze(0)
+        _need(eps, "eps", (eps.shape[0], ribbon.L, ribbon.N))
+        n_real = eps.shape[0]
+    d = ribbon.desc()
+    L = _L.lib()
+    prec = _prec(precision)
+    nbytes = L.rgf_workspace_bytes(ctypes.byref(d), nE, int(n_real), prec, 0, 0)
+    if nbytes == 0:
+        msg = L.rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    ws = _workspace(workspace, nbytes, dev)
+    T = out if out is not None else torch.empty((int(n_real), nE), dtype=torch.float64, device=dev)
+    st = torch.empty((int(n_real), nE), dtype=torch.int32, device=dev)
+    _L.check(L.rgf_conductance(ctypes.byref(d), _vp(energies), nE, _vp(eps), int(n_real), prec,
+                               _vp(T), _vp(st), _vp(ws), ws.numel(), _stream()))
+    if return_status:
+        return T, st
+    return T
+
+
+def lead_self_energy(ribbon, energies, workspace=None):
+    """(Sigma_L [nE, nl, nl], Sigma_R [nE, nr, nr], status [nE]) as complex128,
+    restricted to the slice-1 / slice-L rows that bond to the leads."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    d = ribbon.desc()
+    L = _L.lib()
+    nl = ctypes.c_int32()
+    nr = ctypes.c_int32()
+    _L.check(L.rgf_lead_self_energy(ctypes.byref(d), None, 0, None, None, None,
+                                    ctypes.byref(nl), ctypes.byref(nr), None, 0, None))
+    nbytes = L.rgf_workspace_bytes(ctypes.byref(d), nE, 1, 0, 0, 0)
+    ws = _workspace(workspace, nbytes, dev)
+    sl = torch.empty((nE, nl.value, nl.value, 2), dtype=torch.float64, device=dev)
+    sr = torch.empty((nE, nr.value, nr.value, 2), dtype=torch.float64, device=dev)
+    st = torch.empty((nE,), dtype=torch.int32, device=dev)
+    _L.check(L.rgf_lead_self_energy(ctypes.byref(d), _vp(energies), nE, _vp(sl), _vp(sr),
+                                    _vp(st), None, None, _vp(ws), ws.numel(), _stream()))
+    return torch.view_as_complex(sl), torch.view_as_complex(sr), st
+
+
+def version():
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _L.lib().rgf_version(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value

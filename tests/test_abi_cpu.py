@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/rgf.h, and rejects bad arguments
+before anything is enqueued."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rgf.h")
+LIBP = os.path.join(ROOT, "paper_1107_5300_amd", "librgf.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIBP), reason="librgf.so not built")
+
+
+def _header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rgf_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    names = _header_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def test_version_and_strings():
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    a, b = ctypes.c_int(), ctypes.c_int()
+    assert lib.rgf_version(ctypes.byref(a), ctypes.byref(b)) == 0
+    assert (a.value, b.value) == (1, 0)
+    assert lib.rgf_status_string(-1) == b"RGF_ERR_INVALID_ARG"
+    assert lib.rgf_status_string(-3) == b"RGF_ERR_WORKSPACE"
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("width_n", 1, -1), ("width_n", 100000, -4), ("length_l", 0, -1), ("parity", 2, -1),
+    ("hopping_ev", 0.0, -1), ("hopping_ev", float("nan"), -1), ("eta_ev", 0.0, -1),
+    ("eta_ev", -1e-8, -1), ("eta_ev", float("inf"), -1), ("struct_size", 8, -1),
+])
+def test_invalid_descriptor(field, value, code):
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    d = L.make_desc(20, 10)
+    setattr(d, field, value)
+    rc = lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+                             ctypes.c_void_p(16), None, None, 0, None)
+    assert rc == code
+    assert len(lib.rgf_last_error_message()) > 0
+    assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 0, 0) == 0
+
+
+def test_null_pointers_and_small_workspace():
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    d = L.make_desc(20, 10)
+    need = lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 0, 0)
+    assert need > 0
+    # NULL energies
+    assert lib.rgf_conductance(ctypes.byref(d), None, 4, None, 1, 0, ctypes.c_void_p(256),
+                               None, ctypes.c_void_p(256), need, None) == -1
+    # NULL T_out
+    assert lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(256), 4, None, 1, 0, None,
+                               None, ctypes.c_void_p(256), need, None) == -1
+    # workspace too small
+    assert lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(256), 4, None, 1, 0,
+                               ctypes.c_void_p(256), None, ctypes.c_void_p(256), need - 1,
+                               None) == -3
+    assert b"workspace" in lib.rgf_last_error_message()
+    # misaligned workspace
+    assert lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(256), 4, None, 1, 0,
+                               ctypes.c_void_p(256), None, ctypes.c_void_p(264), need,
+                               None) == -1
+    # bad counts / precision
+    assert lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(256), -1, None, 1, 0,
+                               ctypes.c_void_p(256), None, ctypes.c_void_p(256), need,
+                               None) == -1
+    assert lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(256), 4, None, 0, 0,
+                               ctypes.c_void_p(256), None, ctypes.c_void_p(256), need,
+                               None) == -1
+    assert lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(256), 4, None, 1, 7,
+                               ctypes.c_void_p(256), None, ctypes.c_void_p(256), need,
+                               None) == -1
+    # zero energies is a no-op
+    assert lib.rgf_conductance(ctypes.byref(d), None, 0, None, 1, 0, None, None, None, 0,
+                               None) == 0
+
+
+def test_lead_sizes_query():
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    for N, Lc, par, nl, nr in [(20, 10, 0, 10, 10), (7, 3, 0, 4, 3), (7, 4, 0, 4, 4),
+                               (7, 4, 1, 3, 3), (7, 3, 1, 3, 4)]:
+        d = L.make_desc(N, Lc, par)
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        assert lib.rgf_lead_self_energy(ctypes.byref(d), None, 0, None, None, None,
+                                        ctypes.byref(a), ctypes.byref(b), None, 0, None) == 0
+        assert (a.value, b.value) == (nl, nr), (N, Lc, par)

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Element-by-element on shared seeded inputs. Tolerances (units of 2e^2/h):
+FP64 path |dT| <= 1e-9 * max(1, |T|) on small ribbons (both sides are FP64
+with different but backward-stable elimination orders; observed ~1e-12),
+and the 1e-6 bar of the target on full-size ribbons.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import rgf_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_SMALL = 1e-9
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1107_5300_amd as P
+    P.version()  # loads librgf.so or raises
+    return P
+
+
+def _gpu_T(P, N, L, parity, t, Es, eps=None, precision="fp64", status=False):
+    import torch
+    rib = P.Ribbon(N, L, parity, t, W.ETA)
+    E = torch.tensor(np.asarray(Es, dtype=np.float64), device="cuda")
+    ep = None if eps is None else torch.tensor(np.asarray(eps), device="cuda")
+    T, st = P.conductance(rib, E, ep, precision=precision, return_status=True)
+    torch.cuda.synchronize()
+    if status:
+        return T.cpu().numpy(), st.cpu().numpy()
+    return T.cpu().numpy()
+
+
+# ------------------------------------------------------------------ leads
+
+@pytest.mark.parametrize("N,parity,L", [(2, 0, 3), (7, 0, 3), (7, 1, 4), (8, 0, 5),
+                                        (20, 0, 50), (21, 1, 6), (60, 0, 7), (240, 0, 2000)])
+def test_lead_self_energy_matches_oracle(P, N, parity, L):
+    import torch
+    _say("lead", N, parity, L)
+    Es = np.array([-0.83, -0.2, 0.013, 0.37, 0.91]) * abs(W.T_HOP)
+    rib = P.Ribbon(N, L, parity, W.T_HOP, W.ETA)
+    sl, sr, st = P.lead_self_energy(rib, torch.tensor(Es, device="cuda"))
+    torch.cuda.synchronize()
+    sl, sr, st = sl.cpu().numpy(), sr.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all()
+    iL = np.arange(parity % 2, N, 2)
+    iR = np.arange((L + parity) % 2, N, 2)
+    for j, E in enumerate(Es):
+        ol, orr = O.lead_self_energies(N, L, W.T_HOP, W.ETA, E, parity)
+        ol, orr = ol[np.ix_(iL, iL)], orr[np.ix_(iR, iR)]
+        assert np.abs(sl[j] - ol).max() <= 1e-11 * max(1.0, np.abs(ol).max())
+        assert np.abs(sr[j] - orr).max() <= 1e-11 * max(1.0, np.abs(orr).max())
+
+
+# ------------------------------------------------------------------ small ribbons
+
+@pytest.mark.parametrize("seed", range(48))
+def test_random_small_ribbons(P, seed):
+    N, L, parity, t, eps, E = W.random_case(7000 + seed, n_max=24, l_max=12)
+    _say("small", seed, N, L, parity, t)
+    Es = [E, -0.5 * E + 0.1, 0.77 * abs(t)]
+    got = _gpu_T(P, N, L, parity, t, Es, eps[None])
+    for j, Ej in enumerate(Es):
+        want = O.transmission(N, L, t, W.ETA, Ej, eps, parity)
+        assert abs(got[0, j] - want) <= TOL_SMALL * max(1.0, abs(want)), (j, got[0, j], want)
+
+
+def test_pristine_config1_quantised(P):
+    """Pristine N=20, L=50, 64 energies: equal to the oracle and to M(E)."""
+    _say("pristine_n20")
+    N, L = 20, 50
+    Es = W.energies("pristine_n20")
+    got = _gpu_T(P, N, L, 0, W.T_HOP, Es)[0]
+    want = np.loadtxt(__file__.replace("test_gpu_parity.py", "golden/pristine_n20.txt"))
+    assert np.abs(got - want[:, 1]).max() <= 1e-10
+    assert np.abs(got - want[:, 2]).max() <= 1e-4
+
+
+def test_golden_small_disorder(P):
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "small_disorder.txt"))
+    for row in rows:
+        seed = int(row[0])
+        N, L, parity, t, eps, E = W.random_case(seed, n_max=24, l_max=30)
+        _say("golden", seed, N, L, parity)
+        got = _gpu_T(P, N, L, parity, t, [E], eps[None])[0, 0]
+        assert abs(got - row[6]) <= TOL_SMALL * max(1.0, abs(row[6]))
+
+
+@pytest.mark.parametrize("N", [59, 60, 61, 119, 120, 127, 128, 200, 240, 241, 255, 256])
+def test_widths_span_tiles(P, N):
+    """Every register tiling, even/odd N and ragged padding."""
+    L = 9
+    _say("width", N, L)
+    eps = W.disorder(L, N, 0.5, r=N)
+    Es = np.array([-0.31, 0.024, 0.45]) * abs(W.T_HOP)
+    got = _gpu_T(P, N, L, N % 2, W.T_HOP, Es, eps[None])[0]
+    for j, E in enumerate(Es):
+        want = O.transmission(N, L, W.T_HOP, W.ETA, E, eps, N % 2)
+        assert abs(got[j] - want) <= TOL_SMALL * max(1.0, abs(want)), (N, j, got[j], want)
+
+
+def test_many_realizations_and_energies(P):
+    """Several realizations x energies in one launch (more tuples than slots
+    exercises the persistent loop)."""
+    N, L, R = 30, 16, 5
+    _say("batch", N, L, R)
+    eps = W.disorder_batch(L, N, 0.4, R)
+    Es = np.linspace(-0.9, 0.9, 97) * abs(W.T_HOP)
+    got = _gpu_T(P, N, L, 0, W.T_HOP, Es, eps)
+    for r in range(R):
+        for j in range(0, len(Es), 12):
+            want = O.transmission(N, L, W.T_HOP, W.ETA, Es[j], eps[r], 0)
+            assert abs(got[r, j] - want) <= TOL_SMALL * max(1.0, abs(want))
+
+
+def test_pristine_rows_identical(P):
+    _say("pristine rows")
+    got = _gpu_T(P, 12, 7, 0, W.T_HOP, [0.3, 1.1], None)
+    assert got.shape == (1, 2)
+
+
+# ------------------------------------------------------------------ invariants
+
+def test_invariants_at_scale(P):
+    """0 <= T <= M(E) and T(t) = T(-t) on a wider, longer disordered ribbon."""
+    N, L = 120, 300
+    _say("invariants", N, L)
+    eps = W.disorder(L, N, 0.5, r=1)
+    Es = np.linspace(-0.5, 0.5, 32) * abs(W.T_HOP)
+    a = _gpu_T(P, N, L, 0, W.T_HOP, Es, eps[None])[0]
+    b = _gpu_T(P, N, L, 0, -W.T_HOP, Es, eps[None])[0]
+    M = np.array([O.open_channels(N, E, W.T_HOP) for E in Es])
+    assert (a >= -1e-12).all() and (a <= M + 1e-9).all()
+    assert np.abs(a - b).max() <= 1e-9
+
+
+def test_nan_energy_sets_status(P):
+    _say("nan energy")
+    T, st = _gpu_T(P, 10, 5, 0, W.T_HOP, [0.3, float("nan")], None, status=True)
+    assert st[0, 0] == 0 and np.isfinite(T[0, 0])
+    assert st[0, 1] != 0 and np.isnan(T[0, 1])
+
+
+# ------------------------------------------------------------------ full size
+
+def test_disorder_n240_full_length_sampled(P):
+    """N=240, L=2000 disordered ribbon: the launch configuration of the
+    benchmark, checked against the oracle on sampled energies."""
+    N, L = 240, 2000
+    _say("disorder_n240 sampled", N, L)
+    Es_all = W.energies("disorder_n240")
+    eps = W.disorder(L, N, 0.5, r=0)
+    got = _gpu_T(P, N, L, 0, W.T_HOP, Es_all, eps[None])[0]
+    assert np.isfinite(got).all()
+    M = np.array([O.open_channels(N, E, W.T_HOP) for E in Es_all])
+    assert (got >= -1e-12).all() and (got <= M + 1e-9).all()
+    for j in (37, 200):
+        want = O.transmission(N, L, W.T_HOP, W.ETA, Es_all[j], eps, 0)
+        _say("  oracle E index", j, want, got[j])
+        assert abs(got[j] - want) <= 1e-6
