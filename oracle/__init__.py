@@ -11,14 +11,16 @@ nanoribbons using GPU", Comput. Phys. Commun. 183 (2012) 543 (arXiv:1107.5300).
 Every function is written from the paper's equations (Eq. (1) the Green's
 function, Eq. (2) the conductance, Eq. (3) Dyson's equation, Eqs. (4)-(5) the
 slice recursion) plus the textbook definitions the paper defers to
-(broadening Gamma = i(Sigma - Sigma^dagger), Sancho-Rubio decimation for the
-lead surface Green's function).
+(broadening Gamma = i(Sigma - Sigma^dagger); the lead surface Green's
+function from the Bloch-mode eigenproblem, or from Sancho-Rubio decimation).
 
 Parity status per function (see the pins in tests/test_oracle_*.py):
   transmission_bf        pinned: closed forms (quantised pristine T, 1D chain
                          impurity), symmetries, bounds
   transmission           pinned: == transmission_bf on tiny ribbons
-  lead_self_energies     pinned: closed-form SSH-mode surface GF, fixed-point
+  lead_self_energies     pinned: closed-form surface GF of the decoupled
+                         transverse-mode chains (both routes: Bloch-mode
+                         eigenproblem, default, and Sancho-Rubio), fixed-point
                          residual, sign of Im Sigma
   open_channels          pinned: Bloch band counting of the lead unit cell
   half_gap               pinned: band-structure minimum over a dense k grid
@@ -30,7 +32,9 @@ from .rgf_oracle import (  # noqa: F401
     coupling_mask,
     slice_hamiltonian,
     coupling,
+    coupling_diag,
     sancho_rubio,
+    surface_gf_modes,
     lead_self_energies,
     transmission,
     transmission_rl,

@@ -25,7 +25,9 @@ __all__ = [
     "coupling_mask",
     "slice_hamiltonian",
     "coupling",
+    "coupling_diag",
     "sancho_rubio",
+    "surface_gf_modes",
     "lead_self_energies",
     "transmission",
     "transmission_rl",
@@ -62,15 +64,20 @@ def slice_hamiltonian(N, t, eps_row=None):
 
 def coupling(N, t, i, parity=0):
     """U_i = H_{i,i+1}: hopping block from slice i to slice i+1."""
-    return np.diag(np.where(coupling_mask(N, i, parity), t, 0.0)).astype(np.complex128)
+    return np.diag(coupling_diag(N, t, i, parity)).astype(np.complex128)
+
+
+def coupling_diag(N, t, i, parity=0):
+    """Diagonal of U_i (U_i is diagonal: each row bonds straight ahead or not)."""
+    return np.where(coupling_mask(N, i, parity), t, 0.0)
 
 
 # --------------------------------------------------------------------------
-# Leads: surface Green's function by Sancho-Rubio decimation
-# (M. P. Lopez Sancho, J. M. Lopez Sancho, J. Rubio, J. Phys. F 15 (1985) 851).
-# The paper obtains the lead self-energies at slices 1 and M separately from
-# the recursion (method section); the decimation yields the same retarded
-# surface Green's function.
+# Leads: the paper obtains the lead self-energies at slices 1 and M from an
+# eigenproblem, separately from the recursion (method section). The default
+# here is that route (Bloch modes of the lead); Sancho-Rubio decimation
+# (M. P. Lopez Sancho, J. M. Lopez Sancho, J. Rubio, J. Phys. F 15 (1985) 851)
+# is kept as a second route to the same retarded surface Green's function.
 # --------------------------------------------------------------------------
 
 def sancho_rubio(z, h00, h01, tol=1e-15, maxit=200):
@@ -104,6 +111,34 @@ def sancho_rubio(z, h00, h01, tol=1e-15, maxit=200):
     return np.linalg.inv(z * eye - eps_s), it, converged
 
 
+def surface_gf_modes(z, h00, h01):
+    """Surface Green's function of a semi-infinite stack of identical layers
+    from its Bloch modes: the eigenproblem route of the paper's method section
+    (mode matching as in T. Ando, Phys. Rev. B 44 (1991) 8017).
+
+    Bloch solutions psi_{n+1} = lam psi_n of
+    (z - h00 - lam h01 - h01^T / lam) psi = 0 come from the linear pencil
+    A v = lam B v, v = (psi, lam psi). With eta > 0 exactly m = dim(h00) of
+    them decay into the stack (|lam| < 1; lam = 0 for the null space of
+    h01^T). With U their eigenvectors and F = U diag(lam) U^{-1} the layer-
+    to-layer transfer, the surface layer obeys
+    g_surf = (z - h00 - h01 F)^{-1}.
+    """
+    import scipy.linalg as sla
+    m = h00.shape[0]
+    I = np.eye(m)
+    Z = np.zeros((m, m))
+    A = np.block([[Z, I], [-h01.T, z * I - h00]])
+    B = np.block([[I, Z], [Z, h01]])
+    lam, V = sla.eig(A, B)
+    sel = np.nonzero(np.isfinite(lam) & (np.abs(lam) < 1.0))[0]
+    if len(sel) != m:
+        raise ArithmeticError(f"{len(sel)} decaying modes for a layer of {m} sites")
+    U = V[:m, sel]
+    F = U @ np.diag(lam[sel]) @ np.linalg.inv(U)
+    return np.linalg.inv(z * I - h00 - h01 @ F)
+
+
 def _lead_cells(N, t, L, parity):
     """Two-slice principal layers of the left and right leads.
 
@@ -128,16 +163,24 @@ def _lead_cells(N, t, L, parity):
 
 
 def lead_self_energies(N, L, t, eta, E, parity=0, tol=1e-15, maxit=200,
-                       return_info=False):
+                       return_info=False, method="modes"):
     """Sigma_L (acts on slice 1) and Sigma_R (acts on slice L), N x N each.
 
     Sigma_L = H_{1,0} g_L H_{0,1} = U_0^T g_L[0,0] U_0,
     Sigma_R = H_{L,L+1} g_R H_{L+1,L} = U_L g_R[L+1,L+1] U_L^T.
+    method = "modes": Bloch-mode eigenproblem (surface_gf_modes), the default;
+    method = "decimation": Sancho-Rubio on the dense two-slice cell (loses
+    digits for wide leads and can settle on the advanced solution when the
+    cell's Bloch phase is commensurate; kept as a cross-check).
     """
     z = complex(E, eta)
     (h00_l, h01_l), (h00_r, h01_r) = _lead_cells(N, t, L, parity)
-    gl, itl, okl = sancho_rubio(z, h00_l, h01_l, tol, maxit)
-    gr, itr, okr = sancho_rubio(z, h00_r, h01_r, tol, maxit)
+    if method == "modes":
+        gl, itl, okl = surface_gf_modes(z, h00_l, h01_l), 0, True
+        gr, itr, okr = surface_gf_modes(z, h00_r, h01_r), 0, True
+    else:
+        gl, itl, okl = sancho_rubio(z, h00_l, h01_l, tol, maxit)
+        gr, itr, okr = sancho_rubio(z, h00_r, h01_r, tol, maxit)
     g0 = gl[N:, N:]        # slice 0 block of the left surface cell
     gLp1 = gr[:N, :N]      # slice L+1 block of the right surface cell
     U0 = coupling(N, t, 0, parity)
@@ -197,12 +240,13 @@ def transmission(N, L, t, eta, E, eps=None, parity=0, sigmas=None,
     g = np.linalg.inv(A)
     G1 = g
     for j in range(2, L + 1):
-        U = coupling(N, t, j - 1, parity)          # H_{j-1,j}
-        A = z * eye - Hs[j - 1] - U.T @ g @ U
+        u = coupling_diag(N, t, j - 1, parity)     # H_{j-1,j} = diag(u)
+        # U^T g U and G1 U with U = diag(u), written as row/column scalings
+        A = z * eye - Hs[j - 1] - u[:, None] * g * u[None, :]
         if j == L:
             A = A - sig_r
         g = np.linalg.inv(A)
-        G1 = G1 @ U @ g
+        G1 = (G1 * u[None, :]) @ g
     T = np.real(np.trace(_gamma(sig_l) @ G1 @ _gamma(sig_r) @ G1.conj().T))
     if return_g:
         return T, G1
