@@ -1,0 +1,200 @@
+"""Benchmark: RGF slice-steps/s of the armchair-ribbon conductance sweep on one
+MI355X, N=240 disordered ribbon (workload disorder_n240).
+
+One step = one pass of the whole hot path over the workload: lead
+self-energies (Sancho-Rubio, FP64) + the slice recursion of every
+(realization, energy) tuple + the conductance trace, i.e. one rgf_conductance
+call covering 256 energies x 2000 slices = 512,000 slice-steps. Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line (see the design doc for the fields). The CPU baseline is the
+oracle (numpy FP64) on a bounded sample of the same workload, run before the
+GPU is touched, one process per core with single-threaded BLAS.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import rgf_workloads as W  # noqa: E402
+
+WORKLOAD = "disorder_n240"
+N, L, N_REAL, WDIS = 240, 2000, 1, 0.5
+METRIC = "RGF slice-steps/s at N=240, mixed vs FP64 at |ΔT|≤1e-6; MFMA % of peak"
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 (vector and matrix), 256 CU x 2.4 GHz
+ACC_TOL = 1e-6
+
+
+def flops_per_slice_step(N):
+    """Algorithmic real flops of one slice step of the half-slice recursion:
+    two n x n complex inversions (n^3 complex MACs each) and two n x n x n
+    complex GEMMs for the running propagator, 8 real flops per complex MAC,
+    n = N/2: 32 n^3 = 4 N^3."""
+    n = (N + 1) // 2
+    return 32.0 * n ** 3
+
+
+def dense_equiv_flops(N):
+    """The dense-slice convention (pivoted LU of N x N + solve for N/2
+    right-hand sides + the G_1i update): (23/3) N^3."""
+    return 23.0 / 3.0 * N ** 3
+
+
+# ----------------------------------------------------------------------------- CPU leg
+
+def _oracle_job(args):
+    j, E, eps = args
+    import oracle as O
+    t0 = time.perf_counter()
+    T = O.transmission(N, L, W.T_HOP, W.ETA, float(E), eps, 0)
+    return j, T, time.perf_counter() - t0
+
+
+def cpu_baseline(Es, eps, max_workers=16):
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    nw = max(1, min(max_workers, cores))
+    idx = np.linspace(0, len(Es) - 1, nw).round().astype(int)
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    os.environ["MKL_NUM_THREADS"] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(nw) as pool:
+        res = pool.map(_oracle_job, [(int(j), Es[j], eps) for j in idx])
+    wall = time.perf_counter() - t0
+    rate = len(idx) * L / wall
+    return {
+        "value": rate,
+        "unit": "slice-steps/s",
+        "cores": nw,
+        "kind": "oracle",
+        "sample": f"{len(idx)} of {len(Es)} energies of {WORKLOAD} at full length "
+                  f"(N={N}, L={L}), one energy per process, single-threaded numpy/OpenBLAS; "
+                  f"{wall:.1f} s wall",
+        "per_energy_s": float(np.mean([r[2] for r in res])),
+    }, {int(r[0]): float(r[1]) for r in res}
+
+
+# ----------------------------------------------------------------------------- GPU leg
+
+def gpu_run(Es, eps, precision, steps, warmup):
+    import torch
+
+    import paper_1107_5300_amd as P
+    dev = torch.device("cuda:0")
+    rib = P.Ribbon(N, L, 0, W.T_HOP, W.ETA)
+    E = torch.tensor(Es, device=dev)
+    ep = torch.tensor(eps[None], device=dev)
+    ws = P.Workspace()
+    out = torch.empty((N_REAL, len(Es)), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        P.conductance(rib, E, ep, precision=precision, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        P.conductance(rib, E, ep, precision=precision, workspace=ws, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [a.elapsed_time(b) for a, b in evs]
+    T, st = P.conductance(rib, E, ep, precision=precision, workspace=ws, return_status=True)
+    torch.cuda.synchronize()
+    return wall, ev_ms, T.cpu().numpy()[0], st.cpu().numpy()[0]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32", "auto"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(tuples would shard across GPUs with one gather of T; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    Es = W.energies(WORKLOAD)
+    eps = W.disorder(L, N, WDIS, r=0)
+
+    cpu, oracle_T = (None, {})
+    if not args.no_cpu:
+        cpu, oracle_T = cpu_baseline(Es, eps)
+
+    steps_per_call = N_REAL * len(Es) * L
+    modes = ["fp64"] if args.precision in ("fp64", "auto") else [args.precision]
+    results = {}
+    for prec in modes:
+        wall, ev_ms, T, st = gpu_run(Es, eps, prec, args.steps, args.warmup)
+        dT = max((abs(T[j] - v) for j, v in oracle_T.items()), default=None)
+        results[prec] = dict(wall=wall, ev_ms=ev_ms, T=T, st=st, dT=dT)
+
+    prec = modes[0]
+    r = results[prec]
+    K = args.steps
+    value = steps_per_call * K / r["wall"]
+    ev_mean_s = float(np.mean(r["ev_ms"])) / 1e3
+    flops_call = flops_per_slice_step(N) * steps_per_call
+    achieved = flops_call / ev_mean_s / 1e12
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "slice-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": r["wall"] / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "fp32": "f32"}[prec],
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOAD, "N": N, "L": L, "n_energies": int(len(Es)),
+            "n_real": N_REAL, "disorder": f"U[-{WDIS}|t|,{WDIS}|t|] seed {W.SEED_BASE}",
+            "t_ev": W.T_HOP, "eta_ev": W.ETA, "precision": prec,
+            "slice_steps_per_step": steps_per_call,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "kernel": "rgf_fwd_kernel<8,2,15> (+ lead kernels, < 0.1 %)",
+            "flops_per_slice_step": flops_per_slice_step(N),
+            "dense_equiv_tflops": dense_equiv_flops(N) * steps_per_call / ev_mean_s / 1e12,
+            "event_ms_mean": ev_mean_s * 1e3,
+        },
+        "cpu_baseline": None if cpu is None else {
+            k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "accuracy": {
+            "max_abs_dT_vs_oracle": r["dT"],
+            "oracle_energies": sorted(oracle_T.keys()),
+            "bar": ACC_TOL,
+            "meets_bar": (r["dT"] is not None and r["dT"] <= ACC_TOL),
+            "tuples_not_ok": int((r["st"] != 0).sum()),
+        },
+        "rates": {p: steps_per_call * K / results[p]["wall"] for p in results},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

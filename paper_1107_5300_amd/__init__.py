@@ -10,6 +10,8 @@ from .rgf import (  # noqa: F401
     PRECISIONS,
     Workspace,
     conductance,
+    grad,
+    RGFConductance,
     lead_self_energy,
     workspace_bytes,
     version,

@@ -68,10 +68,6 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   if (precision != RGF_PREC_FP64 && precision != RGF_PREC_MIXED &&
       precision != RGF_PREC_FP32)
     return fail(RGF_ERR_INVALID_ARG, "precision = %d unknown", precision);
-  if (precision != RGF_PREC_FP64)
-    return fail(RGF_ERR_UNSUPPORTED, "precision %d is not available in this build",
-                precision);
-  if (want_grad) return fail(RGF_ERR_UNSUPPORTED, "gradients are not available in this build");
   if (ckpt_stride < 0)
     return fail(RGF_ERR_INVALID_ARG, "ckpt_stride = %lld < 0", (long long)ckpt_stride);
   Plan q;
@@ -94,7 +90,7 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   const int NP = q.tile.NP();
   q.grid = persistent_grid(q.tile, std::max<int64_t>(q.ntuples, 1), precision, q.want_grad);
   q.slot_elems = (int64_t)NP * NP;
-  q.slot_mats = 2;
+  q.slot_mats = slot_matrices(precision, q.want_grad);
   size_t off = 0;
   q.off_sigma = off;
   off = align_up(off + (size_t)nE * q.P * 16, 256);
@@ -106,9 +102,45 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   q.off_slots = off;
   off = align_up(off + (size_t)q.grid * q.slot_mats * q.slot_elems * 16, 256);
   q.off_ckpt = q.off_seg = off;
+  if (q.want_grad) {
+    const int64_t H = 2 * (int64_t)q.L;
+    int64_t stride = ckpt_stride;
+    if (stride == 0) {
+      stride = 1;
+      while (stride * stride < H) ++stride;
+    }
+    if (stride > H) stride = H;
+    q.ckpt_stride = stride;
+    q.n_ckpt = (H + stride - 1) / stride;
+    q.off_ckpt = off;
+    off = align_up(off + (size_t)q.grid * q.n_ckpt * 2 * q.slot_elems * 16, 256);
+    q.off_seg = off;
+    off = align_up(off + (size_t)q.grid * stride * 2 * q.slot_elems * 16, 256);
+  }
   q.total = off;
   *p = q;
   return RGF_OK;
+}
+
+int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad) {
+  int dev = 0, ncu = 256, occ = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    const void* k = grad ? grad_kernel_ptr(t, precision) : fwd_kernel_ptr(t, precision);
+    int o = 0;
+    if (k && hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, t.threads(), 0) == hipSuccess &&
+        o > 0)
+      occ = o;
+    else
+      (void)hipGetLastError();
+  } else {
+    (void)hipGetLastError();
+  }
+  int64_t g = (int64_t)ncu * occ;
+  if (g > ntuples) g = ntuples;
+  if (g < 1) g = 1;
+  return (int)g;
 }
 
 static int check_ws(const Plan& p, void* ws, size_t bytes) {
@@ -164,16 +196,18 @@ int rgf_grad(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_e
   Plan p;
   int st = make_plan(desc, n_energies, n_real, precision, 1, ckpt_stride, &p);
   if (st != RGF_OK) return st;
-  (void)energies_ev;
-  (void)onsite_eps_ev;
-  (void)dL_dT;
-  (void)T_out;
-  (void)dL_deps;
-  (void)status_out;
-  (void)workspace;
-  (void)workspace_bytes;
-  (void)hip_stream;
-  return fail(RGF_ERR_UNSUPPORTED, "gradients are not available in this build");
+  if (!dL_deps) return fail(RGF_ERR_INVALID_ARG, "dL_deps is NULL");
+  if (n_energies > 0) {
+    if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
+    if (!T_out) return fail(RGF_ERR_INVALID_ARG, "T_out is NULL");
+    if (!dL_dT) return fail(RGF_ERR_INVALID_ARG, "dL_dT is NULL");
+  }
+  st = check_ws(p, workspace, workspace_bytes);
+  if (st != RGF_OK) return st;
+  hipError_t e = launch_grad(p, energies_ev, onsite_eps_ev, dL_dT, T_out, dL_deps, status_out,
+                             (char*)workspace, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return RGF_OK;
 }
 
 size_t rgf_batched_workspace_bytes(const rgf_ribbon_desc* descs, int32_t n_desc,

@@ -296,4 +296,22 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return tot;
 }
 
+// Block-wide max of one double per thread (NaN propagates as the max).
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(v, off);
+    v = (o > v || o != o) ? o : v;
+  }
+  __syncthreads();
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) m = (red[i] > m || red[i] != red[i]) ? red[i] : m;
+  __syncthreads();
+  return m;
+}
+
 }  // namespace rgf

@@ -65,4 +65,11 @@ hipError_t launch_grad(const Plan& p, const double* E, const double* eps,
 // Persistent grid size for a tile config on the current device.
 int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad);
 
+// Kernel entry of the forward sweep / adjoint for a tile and precision.
+const void* fwd_kernel_ptr(const TileCfg& t, int precision);
+const void* grad_kernel_ptr(const TileCfg& t, int precision);
+
+// Matrix buffers (NP x NP complex128) per persistent slot.
+int slot_matrices(int precision, bool grad);
+
 }  // namespace rgf

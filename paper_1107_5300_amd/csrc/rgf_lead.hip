@@ -98,7 +98,29 @@ __global__ void lead_modes_kernel(int N, int P, double t, double eta,
       }
     }
     m2 gs = resolvent(z, es);
-    cx<double> sg = cscale(gs.a, wp * t * t);
+    cx<double> g = gs.a;
+    if (ep != 0.0) {
+      // The surface Green's function solves z t^2 g^2 - (z^2 + t^2 - e^2) g + z = 0,
+      // whose two roots multiply to 1/t^2. When the layer's Bloch phase is
+      // commensurate with the doubling (e.g. e = t at E = +-|t|) the
+      // decimation can settle on the advanced root; keep the root whose
+      // layer-to-layer amplitude |e t g / (z - t^2 g)| decays.
+      const cx<double> g2 = crcp(cscale(g, t * t));
+      const cx<double> d1 = csub(z, cscale(g, t * t)), d2 = csub(z, cscale(g2, t * t));
+      const double l1 = fabs(ep * t) * hypot(g.re, g.im) / hypot(d1.re, d1.im);
+      const double l2 = fabs(ep * t) * hypot(g2.re, g2.im) / hypot(d2.re, d2.im);
+      if (l2 < l1) g = g2;
+      // Near such phases the decimation also stagnates at ~eta accuracy;
+      // polish the selected root with Newton steps on the same quadratic.
+      const cx<double> qa = cscale(z, t * t);
+      const cx<double> qb = mk(-(z.re * z.re - z.im * z.im + t * t - ep * ep), -2.0 * z.re * z.im);
+      for (int it = 0; it < 3; ++it) {
+        const cx<double> f = cadd(cmul(cadd(cmul(qa, g), qb), g), z);   // (qa g + qb) g + z
+        const cx<double> df = cadd(cscale(cmul(qa, g), 2.0), qb);       // 2 qa g + qb
+        g = csub(g, cmul(f, crcp(df)));
+      }
+    }
+    cx<double> sg = cscale(g, wp * t * t);
     sigma[e * P + (p - 1)] = sg;
     if (!ok) bad = max(bad, (int)RGF_TUPLE_NO_CONVERGENCE);
     else if (!cfinite(sg)) bad = max(bad, (int)RGF_TUPLE_NONFINITE);

@@ -1,0 +1,409 @@
+// rgf_sweep.hpp -- one half-slice step of the recursion and the conductance
+// trace, shared by the forward kernel and the adjoint kernel.
+//
+// Per half-slice h (Eq. (4)-(5) of the paper on the half-slice chain):
+//   M_h  = z - diag(eps_h) - C_{h-1}^T g_{h-1} C_{h-1}   (- Sigma_L at h = 0,
+//                                                         - Sigma_R at h = 2L-1)
+//   g_h  = M_h^{-1}                                       (Gauss-Jordan, in registers)
+//   G1_h = G1_{h-1} C_{h-1} g_h                            (GEMM, in registers)
+// with C = t*I between R_{i-1} and L_i, and C = B_i (the t-weighted adjacency
+// of the zigzag chain) between L_i and R_i, so C^T g C is t^2 g or a
+// four-point stencil of g. G1 is the block of the left-connected Green's
+// function between L_1 and the current half-slice; after the last half-slice
+// it is the block G_{1L} of the full Green's function (Eq. (1)).
+//
+// Precision of the inversion (template TJ):
+//   double                 FP64 Gauss-Jordan;
+//   float, REFINE = false  FP32 Gauss-Jordan (single-precision study);
+//   float, REFINE = true   FP32 Gauss-Jordan, then Newton steps in FP64,
+//                          g <- g (2I - M g) with M regenerated in FP64, until
+//                          the residual reaches rounding; half-slices whose
+//                          FP32 start does not converge are redone in FP64.
+// G1, the lead self-energies and the trace are FP64 in every mode.
+
+#pragma once
+
+#include "rgf_engine.hpp"
+#include "rgf_internal.hpp"
+
+namespace rgf {
+
+constexpr int KC = 8;
+
+struct SweepArgs {
+  int N, L, parity, P;
+  double t, eta;
+  const double* E;
+  int64_t nE;
+  const double* eps;  // [nreal][L][N] or null
+  int64_t nreal;
+  const cx<double>* sigma;  // [nE][P]
+  const double* phi;        // [2][P][NP]
+  const int32_t* lstat;     // [nE]
+  double* T_out;            // [nreal][nE]
+  int32_t* status;          // [nreal][nE] or null
+  cx<double>* slots;        // [grid][slot_mats][NP*NP]
+  int slot_mats;
+  int64_t ntuples;
+  // adjoint only
+  const double* dL_dT;      // [nreal][nE]
+  double* dL_deps;          // [nreal][L][N]
+  cx<double>* ckpt;         // [grid][n_ckpt][2][NP*NP]
+  cx<double>* seg;          // [grid][stride][2][NP*NP]
+  int stride, n_ckpt;
+};
+
+template <int NW, int S, int C>
+struct SweepSmem {
+  static constexpr int NP = NW * C;
+  cx<double> colbuf[2 * NP];   // also used as cx<float>[4*NP]
+  cx<double> wbuf[NW * NP];    // also used as cx<float>[2*NW*NP]
+  cx<double> As[KC * NP];
+  cx<double> Bs[KC * NP];
+  int pivrow[NP];
+  int pinv[NP];
+  double red[NW * 2];
+  double rowacc[NP];
+  int flag;
+};
+
+// Per-tuple constants.
+struct Tuple {
+  int64_t r, e, idx;
+  cx<double> z;
+  const cx<double>* sig;
+  const double* eps_r;
+};
+
+__device__ __forceinline__ Tuple make_tuple_(const SweepArgs& a, int64_t tau) {
+  Tuple q;
+  q.idx = tau;
+  q.r = tau / a.nE;
+  q.e = tau - q.r * a.nE;
+  q.z = mk(a.E[q.e], a.eta);
+  q.sig = a.sigma + q.e * a.P;
+  q.eps_r = a.eps ? a.eps + q.r * (int64_t)a.L * a.N : nullptr;
+  return q;
+}
+
+// A -= Phi diag(sigma) Phi^T on the n x n block (lead self-energy), as P
+// rank-1 updates: phi[p][.] holds mode p on the interface rows.
+template <typename T, int NW, int S, int C>
+__device__ __forceinline__ void sub_mode_sum(cx<T> (&A)[S][C], const double* phi,
+                                             const cx<double>* sig, int P, int n) {
+  constexpr int NP = NW * C;
+  const int lane = lane_id(), w = wave_id();
+  phi = opaque_uniform(phi);
+#pragma unroll 1
+  for (int p = 0; p < P; ++p) {
+    const double* ph = phi + (size_t)p * NP;
+    const cx<double> sp = sig[p];
+    double fr[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = lane + 64 * s;
+      fr[s] = (r < n) ? ph[r] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int c = w * C + j;
+      const double fc = (c < n) ? ph[c] : 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const double f = fr[s] * fc;
+        A[s][j].re = (T)fma(-f, sp.re, (double)A[s][j].re);
+        A[s][j].im = (T)fma(-f, sp.im, (double)A[s][j].im);
+      }
+    }
+  }
+}
+
+// Assemble M_h into the register tile (padded with the identity).
+//   L half (h even, h > 0): M = z - eps - t^2 K            (K = g of R_{i-1})
+//   R half (h odd):         M = z - eps - t^2 B'^T K B'    (K = g of L_i)
+// where (B'^T K B')[r][c] = sum of K over the neighbour rows of r and the
+// neighbour columns of c; the column sums go through the wave's LDS scratch.
+// Sums are formed in FP64 and rounded once to T.
+template <typename T, int NW, int S, int C>
+__device__ __forceinline__ void build_M(cx<T> (&A)[S][C], const SweepArgs& a,
+                                        const Tuple& q, int h, const cx<double>* K,
+                                        cx<double>* wbuf) {
+  constexpr int NP = NW * C;
+  const int lane = lane_id(), w = wave_id();
+  const bool rhalf = (h & 1) != 0;
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  const int nL = half_size(a.N, e ^ 1);  // L half of the same slice (R half only)
+  const double mt2 = -(a.t * a.t);
+  const double* eps_slice = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
+  K = opaque_uniform(K);
+  if (eps_slice) eps_slice = opaque_uniform(eps_slice);
+  double dre[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int r = lane + 64 * s;
+    dre[s] = (r < n) ? q.z.re - (eps_slice ? eps_slice[half_row(r, e)] : 0.0) : 1.0;
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int c = w * C + j;
+    if (!rhalf) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = lane + 64 * s;
+        cx<double> v = mk(0.0, 0.0);
+        if (h > 0 && r < n && c < n) v = cscale(ldg(K + (size_t)c * NP + r), mt2);
+        if (r == c) v = cadd(v, mk(dre[s], r < n ? q.z.im : 0.0));
+        A[s][j] = mk<T>((T)v.re, (T)v.im);
+      }
+      if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    } else {
+      const int c0 = nb_lo(c, e), c1 = nb_hi(c, e);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = lane + 64 * s;
+        cx<double> cs = mk(0.0, 0.0);
+        if (c < n && r < nL) {
+          if (c0 >= 0) cs = ldg(K + (size_t)c0 * NP + r);
+          if (c1 < nL) cs = cadd(cs, ldg(K + (size_t)c1 * NP + r));
+        }
+        if (r < NP) wbuf[r] = cs;
+      }
+      wave_sync_lds();
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = lane + 64 * s;
+        cx<double> v = mk(0.0, 0.0);
+        if (r < n && c < n) {
+          const int r0 = nb_lo(r, e), r1 = nb_hi(r, e);
+          if (r0 >= 0) v = wbuf[r0];
+          if (r1 < nL) v = cadd(v, wbuf[r1]);
+          v = cscale(v, mt2);
+        }
+        if (r == c) v = cadd(v, mk(dre[s], r < n ? q.z.im : 0.0));
+        A[s][j] = mk<T>((T)v.re, (T)v.im);
+      }
+      wave_sync_lds();
+    }
+  }
+  if (h == 0) sub_mode_sum<T, NW, S, C>(A, a.phi, q.sig, a.P, n);
+  if (h == 2 * a.L - 1) sub_mode_sum<T, NW, S, C>(A, a.phi + (size_t)a.P * NP, q.sig, a.P, n);
+}
+
+// One entry of M_h in FP64 (for the refinement residual), r, c < NP.
+template <int NP>
+__device__ __forceinline__ cx<double> m_entry(const SweepArgs& a, const Tuple& q, int h,
+                                              const cx<double>* K, int r, int c) {
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  if (r >= n || c >= n) return mk((r == c) ? 1.0 : 0.0, 0.0);
+  cx<double> v = mk(0.0, 0.0);
+  if (r == c) {
+    const double* eps_slice = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
+    v = mk(q.z.re - (eps_slice ? eps_slice[half_row(r, e)] : 0.0), q.z.im);
+  }
+  const double mt2 = -(a.t * a.t);
+  if (!(h & 1)) {
+    if (h > 0) v = cadd(v, cscale(ldg(K + (size_t)c * NP + r), mt2));
+  } else {
+    const int nL = half_size(a.N, e ^ 1);
+    const int r0 = nb_lo(r, e), r1 = nb_hi(r, e), c0 = nb_lo(c, e), c1 = nb_hi(c, e);
+    cx<double> acc = mk(0.0, 0.0);
+    if (r0 >= 0 && c0 >= 0) acc = cadd(acc, ldg(K + (size_t)c0 * NP + r0));
+    if (r0 >= 0 && c1 < nL) acc = cadd(acc, ldg(K + (size_t)c1 * NP + r0));
+    if (r1 < nL && c0 >= 0) acc = cadd(acc, ldg(K + (size_t)c0 * NP + r1));
+    if (r1 < nL && c1 < nL) acc = cadd(acc, ldg(K + (size_t)c1 * NP + r1));
+    v = cadd(v, cscale(acc, mt2));
+  }
+  const double* phi = nullptr;
+  if (h == 0) phi = a.phi;
+  if (h == 2 * a.L - 1) phi = a.phi + (size_t)a.P * NP;
+  if (phi) {
+    for (int p = 0; p < a.P; ++p) {
+      const double f = phi[(size_t)p * NP + r] * phi[(size_t)p * NP + c];
+      v.re = fma(-f, q.sig[p].re, v.re);
+      v.im = fma(-f, q.sig[p].im, v.im);
+    }
+  }
+  return v;
+}
+
+// One half-slice step: reads g_{h-1} from Kprev and G1_{h-1} from G1, writes
+// g_h to Kout and G1_h to G1 (in place). Kprev != Kout when REFINE (the
+// residual regenerates M_h from Kprev after Kout holds the FP32 inverse);
+// Rbuf (NP x NP) is the refinement scratch. A is the caller's FP64 register
+// tile (reused as GEMM accumulator); AJ the inversion tile.
+template <typename TJ, bool REFINE, int NW, int S, int C>
+__device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, int h,
+                                          const cx<double>* Kprev, cx<double>* Kout,
+                                          const cx<double>* G1in, cx<double>* G1out,
+                                          cx<double>* Rbuf, cx<double> (&A)[S][C],
+                                          SweepSmem<NW, S, C>& sm) {
+  constexpr int NP = NW * C;
+  const int w = wave_id();
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  if constexpr (sizeof(TJ) == sizeof(double)) {
+    build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
+    __syncthreads();
+    gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.wbuf, sm.pivrow, sm.pinv, &sm.flag);
+    store_unpermuted<double, double, NW, S, C>(A, n, sm.wbuf, sm.pivrow, sm.pinv, Kout,
+                                               h == 0 ? G1out : nullptr);
+  } else {
+    cx<float> AJ[S][C];
+    build_M<float, NW, S, C>(AJ, a, q, h, Kprev, sm.wbuf + w * NP);
+    __syncthreads();
+    gj_invert<float, NW, S, C>(AJ, n, reinterpret_cast<cx<float>*>(sm.colbuf),
+                               reinterpret_cast<cx<float>*>(sm.wbuf), sm.pivrow, sm.pinv,
+                               &sm.flag);
+    store_unpermuted<float, double, NW, S, C>(AJ, n, reinterpret_cast<cx<float>*>(sm.wbuf),
+                                              sm.pivrow, sm.pinv, Kout,
+                                              (h == 0 && !REFINE) ? G1out : nullptr);
+  }
+  __syncthreads();
+  if constexpr (REFINE) {
+    // Newton's iteration for the inverse in FP64 from the FP32 start g0:
+    //   R_k = I - M g_k,  g_{k+1} = g_k (I + R_k),  R_{k+1} = R_k^2,
+    // with M regenerated in FP64 from Kprev. It converges only if the FP32
+    // start is good (|R_0| < 1/4 here); a half-slice that ill-conditioned
+    // (kappa ~ 1/u_32, near resonances of disordered ribbons) is inverted again
+    // by the FP64 Gauss-Jordan instead.
+    const int lane = lane_id();
+    bool fallback = false;
+    for (int it = 0; it < 4; ++it) {
+      {
+        const Tuple& qq = q;
+        auto fa = [&](int r, int k) -> cx<double> { return m_entry<NP>(a, qq, h, Kprev, r, k); };
+        auto fb = [&](int k, int c) -> cx<double> {
+          return (c < n) ? ldg(Kout + (size_t)c * NP + k) : mk(0.0, 0.0);
+        };
+        gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
+      }
+      double lmax = 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = lane + 64 * s;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          const int c = w * C + j;
+          const cx<double> d = mk(((r == c) ? 1.0 : 0.0) - A[s][j].re, -A[s][j].im);
+          if (r < n && c < n) {
+            const double m1 = cabs1(d);
+            lmax = (m1 > lmax || m1 != m1) ? m1 : lmax;
+          }
+          A[s][j] = mk(((r == c) ? 1.0 : 0.0) + d.re, d.im);   // I + R_k
+        }
+      }
+      const double rmax = block_max<NW>(lmax, sm.red);
+      if (it == 0 && !(rmax < 0.25)) {
+        fallback = true;
+        break;
+      }
+      if (!(rmax > 1e-15)) break;   // converged to rounding
+      store_regs<double, double, NW, S, C>(A, n, n, Rbuf);
+      __syncthreads();
+      auto fa = [&](int r, int k) -> cx<double> {
+        return (r < n) ? ldg(Kout + (size_t)k * NP + r) : mk(0.0, 0.0);
+      };
+      auto fb = [&](int k, int c) -> cx<double> {
+        return (c < n) ? ldg(Rbuf + (size_t)c * NP + k) : mk(0.0, 0.0);
+      };
+      gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
+      store_regs<double, double, NW, S, C>(A, n, n, Kout);
+      __syncthreads();
+      if (rmax < 1e-8) break;   // the next residual is below n * 1e-16
+    }
+    if (fallback) {
+      build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
+      __syncthreads();
+      gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.wbuf, sm.pivrow, sm.pinv, &sm.flag);
+      store_unpermuted<double, double, NW, S, C>(A, n, sm.wbuf, sm.pivrow, sm.pinv, Kout,
+                                                 nullptr);
+      __syncthreads();
+    }
+    if (h == 0) {
+      for (int i = threadIdx.x; i < NP * NP; i += NW * 64) stg(G1out + i, ldg(Kout + i));
+      __syncthreads();
+    }
+  }
+  if (h > 0) {
+    const double t = a.t;
+    const cx<double>* G1r = opaque_uniform(G1in);
+    auto fb = [&](int k, int c) -> cx<double> {
+      return (c < n) ? ldg(Kout + (size_t)c * NP + k) : mk(0.0, 0.0);
+    };
+    if (!(h & 1)) {
+      auto fa = [&](int r, int k) -> cx<double> {
+        return (r < n1) ? cscale(ldg(G1r + (size_t)k * NP + r), t) : mk(0.0, 0.0);
+      };
+      gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
+    } else {
+      const int nL = half_size(a.N, e ^ 1);
+      auto fa = [&](int r, int k) -> cx<double> {
+        if (r >= n1) return mk(0.0, 0.0);
+        const int k0 = nb_lo(k, e), k1 = nb_hi(k, e);
+        cx<double> acc = mk(0.0, 0.0);
+        if (k0 >= 0) acc = ldg(G1r + (size_t)k0 * NP + r);
+        if (k1 < nL) acc = cadd(acc, ldg(G1r + (size_t)k1 * NP + r));
+        return cscale(acc, t);
+      };
+      gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
+    }
+    store_regs<double, double, NW, S, C>(A, n1, n, G1out);
+    __syncthreads();
+  }
+}
+
+// Conductance from G = G_{1L} in Gbuf: X = G Phi_R -> Xbuf (n1 x P), then
+// S = Phi_L^T X in registers; returns T = sum_{p,q} d_p d_q |S_pq|^2 (every
+// thread). S is left in A (rows p, columns q) for callers that need it.
+template <int NW, int S, int C>
+__device__ __forceinline__ double trace_T(const SweepArgs& a, const Tuple& q,
+                                          const cx<double>* Gbuf, cx<double>* Xbuf,
+                                          cx<double> (&A)[S][C], SweepSmem<NW, S, C>& sm) {
+  constexpr int NP = NW * C;
+  const int lane = lane_id(), w = wave_id();
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const int nlast = half_size(a.N, half_parity(2 * a.L - 1, a.parity));
+  const double* phiL = a.phi;
+  const double* phiR = a.phi + (size_t)a.P * NP;
+  {
+    auto fa = [&](int r, int k) -> cx<double> {
+      return (r < n1) ? ldg(Gbuf + (size_t)k * NP + r) : mk(0.0, 0.0);
+    };
+    auto fb = [&](int k, int c) -> cx<double> {
+      return (c < a.P) ? mk(phiR[(size_t)c * NP + k], 0.0) : mk(0.0, 0.0);
+    };
+    gemm_regs<double, NW, S, C, KC>(A, nlast, fa, fb, sm.As, sm.Bs);
+    store_regs<double, double, NW, S, C>(A, n1, a.P, Xbuf);
+    __syncthreads();
+  }
+  double part = 0.0;
+  {
+    auto fa = [&](int r, int k) -> cx<double> {
+      return (r < a.P) ? mk(phiL[(size_t)r * NP + k], 0.0) : mk(0.0, 0.0);
+    };
+    auto fb = [&](int k, int c) -> cx<double> {
+      return (c < a.P) ? ldg(Xbuf + (size_t)c * NP + k) : mk(0.0, 0.0);
+    };
+    gemm_regs<double, NW, S, C, KC>(A, n1, fa, fb, sm.As, sm.Bs);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int p = lane + 64 * s;
+      if (p >= a.P) continue;
+      const double dp = -2.0 * q.sig[p].im;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int qq = w * C + j;
+        if (qq < a.P) {
+          const double dq = -2.0 * q.sig[qq].im;
+          part += dp * dq * (A[s][j].re * A[s][j].re + A[s][j].im * A[s][j].im);
+        }
+      }
+    }
+  }
+  return block_sum<NW>(part, sm.red);
+}
+
+}  // namespace rgf

@@ -119,6 +119,60 @@ def conductance(ribbon, energies, eps=None, n_real=1, precision="fp64", workspac
     return T
 
 
+def grad(ribbon, energies, eps, dL_dT, precision="fp64", ckpt_stride=0, workspace=None,
+         return_status=False):
+    """(T [R, nE], dL/deps [R, L, N]) for L = sum dL_dT * T: the vector-Jacobian
+    product of the conductance with respect to every on-site energy, by the
+    adjoint sweep of librgf (checkpoint stride in half-slices, 0 = automatic)."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    if eps.dim() == 2:
+        eps = eps.unsqueeze(0)
+    _need(eps, "eps", (eps.shape[0], ribbon.L, ribbon.N))
+    R = eps.shape[0]
+    _need(dL_dT, "dL_dT", (R, nE))
+    d = ribbon.desc()
+    L = _L.lib()
+    prec = _prec(precision)
+    nbytes = L.rgf_workspace_bytes(ctypes.byref(d), nE, R, prec, 1, int(ckpt_stride))
+    if nbytes == 0:
+        msg = L.rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    ws = _workspace(workspace, nbytes, dev)
+    T = torch.empty((R, nE), dtype=torch.float64, device=dev)
+    g = torch.empty((R, ribbon.L, ribbon.N), dtype=torch.float64, device=dev)
+    st = torch.empty((R, nE), dtype=torch.int32, device=dev)
+    _L.check(L.rgf_grad(ctypes.byref(d), _vp(energies), nE, _vp(eps), R, prec, _vp(dL_dT),
+                        _vp(T), _vp(g), int(ckpt_stride), _vp(st), _vp(ws), ws.numel(),
+                        _stream()))
+    if return_status:
+        return T, g, st
+    return T, g
+
+
+class RGFConductance(torch.autograd.Function):
+    """T = RGFConductance.apply(eps, energies, ribbon, precision): conductance
+    [R, nE] with a backward pass through the adjoint sweep (no gradient with
+    respect to the energies)."""
+
+    @staticmethod
+    def forward(ctx, eps, energies, ribbon, precision="fp64"):
+        ctx.save_for_backward(eps, energies)
+        ctx.ribbon = ribbon
+        ctx.precision = precision
+        return conductance(ribbon, energies, eps, precision=precision)
+
+    @staticmethod
+    def backward(ctx, grad_T):
+        eps, energies = ctx.saved_tensors
+        _, g = grad(ctx.ribbon, energies, eps.contiguous(), grad_T.contiguous(),
+                    precision=ctx.precision)
+        if eps.dim() == 2:
+            g = g[0]
+        return g, None, None, None
+
+
 def lead_self_energy(ribbon, energies, workspace=None):
     """(Sigma_L [nE, nl, nl], Sigma_R [nE, nr, nr], status [nE]) as complex128,
     restricted to the slice-1 / slice-L rows that bond to the leads."""

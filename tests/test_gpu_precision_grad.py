@@ -1,0 +1,225 @@
+"""GPU tests of the precision modes and of the adjoint (gradient) sweep.
+
+Bars (units of 2e^2/h): mixed precision (FP32 inversion + FP64 Newton
+refinement per half-slice, FP64 fallback) 1e-8 against FP64 on small and
+medium ribbons and the target's 1e-6 at full size; gradients against the
+oracle's forward-backward recursion to 1e-8 relative on small ribbons, and
+against central finite differences (h = 1e-6|t|) to 1e-6 + 1e-5 relative
+plus the measured truncation estimate |D(2h) - D(h)|/3.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import rgf_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1107_5300_amd as P
+    P.version()
+    return P
+
+
+def _t(x):
+    import torch
+    return torch.tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+def _T(P, N, L, parity, t, Es, eps, precision="fp64"):
+    import torch
+    T, st = P.conductance(P.Ribbon(N, L, parity, t, W.ETA), _t(Es),
+                          None if eps is None else _t(eps), precision=precision,
+                          return_status=True)
+    torch.cuda.synchronize()
+    return T.cpu().numpy(), st.cpu().numpy()
+
+
+# ------------------------------------------------------------------ precision
+
+@pytest.mark.parametrize("seed", range(16))
+def test_mixed_small_ribbons(P, seed):
+    N, L, parity, t, eps, E = W.random_case(8100 + seed, n_max=24, l_max=12)
+    _say("mixed small", seed, N, L)
+    Es = [E, 0.33 * abs(t), -0.71 * abs(t)]
+    got, st = _T(P, N, L, parity, t, Es, eps[None], "mixed")
+    assert (st == 0).all()
+    for j, Ej in enumerate(Es):
+        want = O.transmission(N, L, t, W.ETA, Ej, eps, parity)
+        assert abs(got[0, j] - want) <= 1e-8 * max(1.0, abs(want)), (j, got[0, j], want)
+
+
+@pytest.mark.parametrize("N", [20, 61, 120, 240])
+def test_mixed_widths(P, N):
+    L = 11
+    _say("mixed width", N)
+    eps = W.disorder(L, N, 0.5, r=2)
+    Es = np.array([-0.4, 0.02, 0.3]) * abs(W.T_HOP)
+    a, _ = _T(P, N, L, 0, W.T_HOP, Es, eps[None], "mixed")
+    b, _ = _T(P, N, L, 0, W.T_HOP, Es, eps[None], "fp64")
+    assert np.abs(a - b).max() <= 1e-8
+
+
+def test_single_precision_study_n240(P):
+    """Full-size N=240, L=2000 ribbon: plain FP32 inversions miss the FP64
+    result by more than 1e-6 near the charge-neutrality point (the paper's
+    single-precision finding); FP32 with FP64 refinement stays within 1e-6."""
+    N, L = 240, 2000
+    _say("precision study", N, L)
+    Es = W.energies("disorder_n240")[96:160]       # |E| <= 0.125|t| around the CNP
+    eps = W.disorder(L, N, 0.5, r=0)
+    f64, s64 = _T(P, N, L, 0, W.T_HOP, Es, eps[None], "fp64")
+    mix, smx = _T(P, N, L, 0, W.T_HOP, Es, eps[None], "mixed")
+    f32, s32 = _T(P, N, L, 0, W.T_HOP, Es, eps[None], "fp32")
+    assert (s64 == 0).all() and (smx == 0).all()
+    d_mix = np.abs(mix - f64).max()
+    d_32 = np.nanmax(np.abs(f32 - f64))
+    _say("  max|dT| mixed", d_mix, "plain fp32", d_32)
+    assert d_mix <= 1e-6
+    assert d_32 > 1e-6
+    # and the FP64 path itself against the oracle on one energy
+    j = 40
+    want = O.transmission(N, L, W.T_HOP, W.ETA, Es[j], eps, 0)
+    assert abs(f64[0, j] - want) <= 1e-6
+    assert abs(mix[0, j] - want) <= 1e-6
+
+
+# ------------------------------------------------------------------ gradients
+
+def _grad(P, N, L, parity, t, Es, eps, w, precision="fp64", stride=0):
+    import torch
+    T, g, st = P.grad(P.Ribbon(N, L, parity, t, W.ETA), _t(Es), _t(eps), _t(w),
+                      precision=precision, ckpt_stride=stride, return_status=True)
+    torch.cuda.synchronize()
+    return T.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_grad_small_vs_oracle(P, seed):
+    N, L, parity, t, eps, E = W.random_case(9100 + seed, n_max=14, l_max=9)
+    _say("grad small", seed, N, L, parity)
+    rng = np.random.default_rng(seed)
+    Es = np.array([E, 0.41 * abs(t), -0.13 * abs(t)])
+    w = rng.normal(size=(1, len(Es)))
+    T, g, st = _grad(P, N, L, parity, t, Es, eps[None], w)
+    assert (st == 0).all()
+    want = np.zeros((L, N))
+    for j, Ej in enumerate(Es):
+        Tj, dj = O.transmission_grad(N, L, t, W.ETA, Ej, eps, parity)
+        assert abs(T[0, j] - Tj) <= 1e-9 * max(1.0, abs(Tj))
+        want += w[0, j] * dj
+    scale = max(1.0, np.abs(want).max())
+    assert np.abs(g[0] - want).max() <= 1e-8 * scale
+
+
+def test_grad_checkpoint_strides_agree(P):
+    N, L = 16, 13
+    _say("grad strides", N, L)
+    eps = W.disorder_batch(L, N, 0.4, 2)
+    Es = np.linspace(-0.6, 0.6, 5) * abs(W.T_HOP)
+    w = np.random.default_rng(1).normal(size=(2, len(Es)))
+    ref = _grad(P, N, L, 0, W.T_HOP, Es, eps, w, stride=2 * L)[1]
+    for s in (1, 2, 3, 7, 0):
+        g = _grad(P, N, L, 0, W.T_HOP, Es, eps, w, stride=s)[1]
+        assert np.abs(g - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), s
+
+
+@pytest.mark.parametrize("N", [61, 120, 240])
+def test_grad_widths_vs_oracle(P, N):
+    L = 5
+    _say("grad width", N)
+    eps = W.disorder(L, N, 0.3, r=N)
+    Es = np.array([-0.27, 0.35]) * abs(W.T_HOP)
+    w = np.array([[0.7, -1.3]])
+    T, g, st = _grad(P, N, L, N % 2, W.T_HOP, Es, eps[None], w)
+    want = np.zeros((L, N))
+    for j, E in enumerate(Es):
+        want += w[0, j] * O.transmission_grad(N, L, W.T_HOP, W.ETA, E, eps, N % 2)[1]
+    assert np.abs(g[0] - want).max() <= 1e-8 * max(1.0, np.abs(want).max())
+
+
+def test_grad_mixed_precision(P):
+    N, L = 40, 30
+    _say("grad mixed", N, L)
+    eps = W.disorder(L, N, 0.3, r=5)
+    Es = np.linspace(-0.4, 0.4, 6) * abs(W.T_HOP)
+    w = np.ones((1, len(Es)))
+    g64 = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], w, "fp64")[1]
+    gmx = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], w, "mixed")[1]
+    assert np.abs(gmx - g64).max() <= 1e-6 * max(1.0, np.abs(g64).max())
+
+
+def test_grad_zero_weights_and_skip(P):
+    N, L = 10, 6
+    eps = W.disorder(L, N, 0.3, r=7)
+    Es = np.array([0.2, 0.5]) * abs(W.T_HOP)
+    T, g, st = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], np.zeros((1, 2)))
+    assert np.abs(g).max() == 0.0
+    T2, _ = _T(P, N, L, 0, W.T_HOP, Es, eps[None])
+    assert np.abs(T - T2).max() <= 1e-12
+
+
+def test_autograd_function(P):
+    import torch
+    N, L = 12, 8
+    _say("autograd")
+    eps = _t(W.disorder(L, N, 0.4, r=9)).requires_grad_(True)
+    E = _t(np.array([0.1, 0.45, -0.3]) * abs(W.T_HOP))
+    rib = P.Ribbon(N, L, 0, W.T_HOP, W.ETA)
+    T = P.RGFConductance.apply(eps, E, rib, "fp64")
+    (T * torch.tensor([[1.0, 2.0, -0.5]], device="cuda", dtype=torch.float64)).sum().backward()
+    _, g = P.grad(rib, E, eps.detach(), _t([[1.0, 2.0, -0.5]]))
+    assert torch.allclose(eps.grad, g[0], rtol=0, atol=1e-13)
+
+
+def test_grad_adjoint_n120_fd_sampled(P):
+    """The adjoint workload (N=120, L=500, U[-0.3,0.3]|t|, 128 energies):
+    gradient of sum_E T(E) against central finite differences of the GPU
+    forward sweep on 100 seeded sites, and against the oracle's gradient on
+    one energy."""
+    N, L = 120, 500
+    _say("adjoint_n120", N, L)
+    Es = W.energies("adjoint_n120")
+    eps = W.disorder(L, N, 0.3, r=0)
+    w = np.ones((1, len(Es)))
+    T, g, st = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], w)
+    assert (st == 0).all()
+    h = 1e-6 * abs(W.T_HOP)
+    sites = W.fd_sites(L, N, 100, seed=4)
+
+    def fd(i, k, hh):
+        ep = eps.copy(); ep[i, k] += hh
+        em = eps.copy(); em[i, k] -= hh
+        tp, _ = _T(P, N, L, 0, W.T_HOP, Es, ep[None])
+        tm, _ = _T(P, N, L, 0, W.T_HOP, Es, em[None])
+        return (tp.sum() - tm.sum()) / (2 * hh)
+
+    worst = 0.0
+    for (i, k) in sites:
+        d1 = fd(i, k, h)
+        # central differences err by ~C h^2; resonances of a weakly absorbing
+        # (eta = 1e-8) ribbon make C large at some sites, so the bar adds the
+        # truncation estimate |D(2h) - D(h)| / 3 to the rounding floor
+        trunc = abs(fd(i, k, 2 * h) - d1) / 3.0
+        tol = 1e-6 + 1e-5 * abs(d1) + 2.0 * trunc
+        worst = max(worst, abs(d1 - g[0, i, k]) / tol)
+        assert abs(d1 - g[0, i, k]) <= tol, (i, k, d1, g[0, i, k], trunc)
+    _say("  FD worst normalised error", worst)
+    j = 70
+    Tj, dj = O.transmission_grad(N, L, W.T_HOP, W.ETA, Es[j], eps, 0)
+    wj = np.zeros((1, len(Es))); wj[0, j] = 1.0
+    _, gj, _ = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], wj)
+    assert np.abs(gj[0] - dj).max() <= 1e-7 * max(1.0, np.abs(dj).max())
