@@ -151,6 +151,22 @@ int rgf_lead_self_energy(const rgf_ribbon_desc* desc, const double* energies_ev,
                          int32_t* nl_out, int32_t* nr_out, void* workspace,
                          size_t workspace_bytes, void* hip_stream);
 
+/* Autotuner for the register tiling of the slice recursion (the batching
+ * form of the method: tile shape and tuples in flight per compute unit).
+ * Times every candidate tiling that holds this width, and one or two
+ * persistent-grid sizes each, on a short synthetic sweep of the same width
+ * (pristine ribbon, min(L, 8) slices, one tuple per slot), synchronising the
+ * stream, and remembers the fastest for (width class, precision) in this
+ * process; later plans for that width class use it, including
+ * rgf_workspace_bytes, so tune before sizing workspaces. Thread-safe. Not
+ * for use inside stream capture. The workspace must hold
+ * rgf_autotune_workspace_bytes(desc, precision) bytes.
+ * chosen_out (may be NULL) receives NW * 10000 + S * 1000 + C * 10 + slots
+ * per compute unit of the chosen configuration. */
+size_t rgf_autotune_workspace_bytes(const rgf_ribbon_desc* desc, int precision);
+int rgf_autotune(const rgf_ribbon_desc* desc, int precision, void* workspace,
+                 size_t workspace_bytes, void* hip_stream, int32_t* chosen_out);
+
 /* Static descriptions. rgf_last_error_message is thread-local and describes
  * the last non-OK return of this thread. */
 const char* rgf_status_string(int status);

@@ -10,9 +10,11 @@ from .rgf import (  # noqa: F401
     PRECISIONS,
     Workspace,
     conductance,
+    conductance_batched,
     grad,
     RGFConductance,
     lead_self_energy,
     workspace_bytes,
     version,
+    autotune,
 )

@@ -35,6 +35,8 @@ EXPORTED = (
     "rgf_batched_workspace_bytes",
     "rgf_conductance_batched",
     "rgf_lead_self_energy",
+    "rgf_autotune_workspace_bytes",
+    "rgf_autotune",
     "rgf_status_string",
     "rgf_last_error_message",
     "rgf_version",
@@ -84,6 +86,10 @@ def _declare(lib):
     lib.rgf_lead_self_energy.restype = _int
     lib.rgf_lead_self_energy.argtypes = [_pdesc, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                          _vp]
+    lib.rgf_autotune_workspace_bytes.restype = _sz
+    lib.rgf_autotune_workspace_bytes.argtypes = [_pdesc, _int]
+    lib.rgf_autotune.restype = _int
+    lib.rgf_autotune.argtypes = [_pdesc, _int, _vp, _sz, _vp, ctypes.POINTER(_i32)]
     lib.rgf_status_string.restype = ctypes.c_char_p
     lib.rgf_status_string.argtypes = [_int]
     lib.rgf_last_error_message.restype = ctypes.c_char_p

@@ -33,8 +33,21 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False, jobs=None):
-    """Compile every source to an object in parallel, then link librgf.so."""
+def _stale(obj, src):
+    """True if obj is missing or older than its source or any csrc header /
+    include/rgf.h (every translation unit may include them)."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src), os.path.join(os.path.dirname(HERE), "include", "rgf.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose=False, jobs=None, incremental=False):
+    """Compile every source to an object in parallel, then link librgf.so.
+    incremental=True skips objects that are newer than their inputs (for
+    development; the default always recompiles)."""
     cc = hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -43,6 +56,8 @@ def build(verbose=False, jobs=None):
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
+        if incremental and not _stale(obj, src):
+            continue
         cmd = [cc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [cc, "-x", "hip"] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -73,5 +88,5 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(LIB)

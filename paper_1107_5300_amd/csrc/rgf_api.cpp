@@ -8,7 +8,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "rgf_internal.hpp"
 
@@ -88,7 +92,12 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   if (!pick_tile(q.nmax, precision, &q.tile))
     return fail(RGF_ERR_UNSUPPORTED, "width_n = %d exceeds the register tiling", q.N);
   const int NP = q.tile.NP();
-  q.grid = persistent_grid(q.tile, std::max<int64_t>(q.ntuples, 1), precision, q.want_grad);
+  {
+    int tid = 0, per_cu = 0;
+    if (!q.want_grad && tuned_choice(q.nmax, precision, &tid, &per_cu)) q.per_cu = per_cu;
+  }
+  q.grid = persistent_grid(q.tile, std::max<int64_t>(q.ntuples, 1), precision, q.want_grad,
+                           q.per_cu);
   q.slot_elems = (int64_t)NP * NP;
   q.slot_mats = slot_matrices(precision, q.want_grad);
   size_t off = 0;
@@ -122,7 +131,26 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   return RGF_OK;
 }
 
-int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad) {
+namespace {
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tuned;  // (n, prec) -> (tile, per_cu)
+}  // namespace
+
+bool tuned_choice(int n, int precision, int* tile_id, int* per_cu) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find({n, precision});
+  if (it == g_tuned.end()) return false;
+  *tile_id = it->second.first;
+  *per_cu = it->second.second;
+  return true;
+}
+
+void set_tuned_choice(int n, int precision, int tile_id, int per_cu) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[{n, precision}] = {tile_id, per_cu};
+}
+
+int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad, int per_cu) {
   int dev = 0, ncu = 256, occ = 1;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
@@ -137,6 +165,7 @@ int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad)
   } else {
     (void)hipGetLastError();
   }
+  if (per_cu > 0 && per_cu < occ) occ = per_cu;
   int64_t g = (int64_t)ncu * occ;
   if (g > ntuples) g = ntuples;
   if (g < 1) g = 1;
@@ -210,15 +239,35 @@ int rgf_grad(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_e
   return RGF_OK;
 }
 
+// Ribbons of several widths in one call: one persistent launch per ribbon
+// on the caller's stream, most expensive (N^3 L) first; the workspace is
+// reused from one launch to the next (stream order), so it is sized by the
+// largest plan. The whole sequence can be captured into a hipGraph.
+static int batched_plans(const rgf_ribbon_desc* descs, int32_t n_desc, int64_t n_energies,
+                         int64_t n_real, int precision, Plan* plans, size_t* bytes) {
+  if (!descs) return fail(RGF_ERR_INVALID_ARG, "descs is NULL");
+  if (n_desc < 1 || n_desc > 64)
+    return fail(RGF_ERR_INVALID_ARG, "n_desc = %d outside [1, 64]", n_desc);
+  size_t mx = 0;
+  for (int d = 0; d < n_desc; ++d) {
+    int st = make_plan(&descs[d], n_energies, n_real, precision, 0, 0, &plans[d]);
+    if (st != RGF_OK) {
+      std::string m = rgf_last_error_message();
+      return fail(st, "descs[%d]: %s", d, m.c_str());
+    }
+    mx = std::max(mx, plans[d].total);
+  }
+  *bytes = std::max<size_t>(mx, 256);
+  return RGF_OK;
+}
+
 size_t rgf_batched_workspace_bytes(const rgf_ribbon_desc* descs, int32_t n_desc,
                                    int64_t n_energies, int64_t n_real, int precision) {
-  (void)descs;
-  (void)n_desc;
-  (void)n_energies;
-  (void)n_real;
-  (void)precision;
-  fail(RGF_ERR_UNSUPPORTED, "batched ribbons are not available in this build");
-  return 0;
+  Plan plans[64];
+  size_t bytes = 0;
+  if (batched_plans(descs, n_desc, n_energies, n_real, precision, plans, &bytes) != RGF_OK)
+    return 0;
+  return bytes;
 }
 
 int rgf_conductance_batched(const rgf_ribbon_desc* descs, int32_t n_desc,
@@ -227,21 +276,172 @@ int rgf_conductance_batched(const rgf_ribbon_desc* descs, int32_t n_desc,
                             const double* onsite_eps_ev, int64_t n_real, int precision,
                             double* T_out, int32_t* status_out, void* workspace,
                             size_t workspace_bytes, void* hip_stream) {
-  (void)descs;
-  (void)n_desc;
-  (void)eps_offsets;
-  (void)T_offsets;
-  (void)energies_ev;
-  (void)n_energies;
-  (void)onsite_eps_ev;
-  (void)n_real;
+  Plan plans[64];
+  size_t bytes = 0;
+  int st = batched_plans(descs, n_desc, n_energies, n_real, precision, plans, &bytes);
+  if (st != RGF_OK) return st;
+  if (n_energies == 0) return RGF_OK;
+  if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
+  if (!T_out) return fail(RGF_ERR_INVALID_ARG, "T_out is NULL");
+  if (!T_offsets) return fail(RGF_ERR_INVALID_ARG, "T_offsets is NULL");
+  if (onsite_eps_ev && !eps_offsets) return fail(RGF_ERR_INVALID_ARG, "eps_offsets is NULL");
+  for (int d = 0; d < n_desc; ++d) {
+    if (T_offsets[d] < 0 || (onsite_eps_ev && eps_offsets[d] < 0))
+      return fail(RGF_ERR_INVALID_ARG, "negative offset for descs[%d]", d);
+  }
+  if (workspace_bytes < bytes)
+    return fail(RGF_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, bytes);
+  if (!workspace || ((uintptr_t)workspace) % 256 != 0)
+    return fail(RGF_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  int order[64];
+  for (int d = 0; d < n_desc; ++d) order[d] = d;
+  std::stable_sort(order, order + n_desc, [&](int x, int y) {
+    const double cx = (double)plans[x].N * plans[x].N * plans[x].N * plans[x].L;
+    const double cy = (double)plans[y].N * plans[y].N * plans[y].N * plans[y].L;
+    return cx > cy;
+  });
+  for (int i = 0; i < n_desc; ++i) {
+    const int d = order[i];
+    const double* eps = onsite_eps_ev ? onsite_eps_ev + eps_offsets[d] : nullptr;
+    hipError_t e = launch_forward(plans[d], energies_ev, eps, T_out + T_offsets[d],
+                                  status_out ? status_out + T_offsets[d] : nullptr,
+                                  (char*)workspace, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return RGF_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+constexpr int kTuneL = 8;
+
+struct TuneShape {
+  int64_t nE;
+};
+
+int tune_plan(const rgf_ribbon_desc* desc, int precision, rgf_ribbon_desc* dd,
+              TuneShape* ts) {
+  int st = validate_desc(desc);
+  if (st != RGF_OK) return st;
+  *dd = *desc;
+  dd->length_l = std::min(desc->length_l, kTuneL);
+  int dev = 0, ncu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    ncu = prop.multiProcessorCount;
+  else
+    (void)hipGetLastError();
+  ts->nE = (int64_t)ncu * 4;  // enough tuples for every grid size tried
   (void)precision;
-  (void)T_out;
-  (void)status_out;
-  (void)workspace;
-  (void)workspace_bytes;
-  (void)hip_stream;
-  return fail(RGF_ERR_UNSUPPORTED, "batched ribbons are not available in this build");
+  return RGF_OK;
+}
+
+size_t tune_bytes_for(const rgf_ribbon_desc* dd, int64_t nE, int precision) {
+  // energies + T of the trial sweep, then the largest plan over all candidate
+  // tilings at their full persistent grid
+  const int n = (dd->width_n + 1) / 2;
+  const int P = lead_modes(dd->width_n);
+  const int mats = slot_matrices(precision, false);
+  size_t mx = 0;
+  for (int i = 0; i < tile_count(); ++i) {
+    const TileCfg t = tile_at(i);
+    if (t.NP() < n || 64 * t.S < t.NP()) continue;
+    const size_t NP = (size_t)t.NP();
+    const size_t head = align_up((size_t)nE * P * 16, 256) + align_up(2 * (size_t)P * NP * 8, 256) +
+                        align_up((size_t)nE * 4, 256);
+    const size_t slots = (size_t)persistent_grid(t, nE, precision, false) * mats * NP * NP * 16;
+    mx = std::max(mx, head + align_up(slots, 256));
+  }
+  return align_up((size_t)nE * 16, 256) + mx;
+}
+}  // namespace
+
+size_t rgf_autotune_workspace_bytes(const rgf_ribbon_desc* desc, int precision) {
+  rgf_ribbon_desc dd;
+  TuneShape ts;
+  if (tune_plan(desc, precision, &dd, &ts) != RGF_OK) return 0;
+  if (precision < 0 || precision > 2) {
+    fail(RGF_ERR_INVALID_ARG, "precision = %d unknown", precision);
+    return 0;
+  }
+  return tune_bytes_for(&dd, ts.nE, precision);
+}
+
+int rgf_autotune(const rgf_ribbon_desc* desc, int precision, void* workspace,
+                 size_t workspace_bytes, void* hip_stream, int32_t* chosen_out) {
+  rgf_ribbon_desc dd;
+  TuneShape ts;
+  int st = tune_plan(desc, precision, &dd, &ts);
+  if (st != RGF_OK) return st;
+  if (precision < 0 || precision > 2)
+    return fail(RGF_ERR_INVALID_ARG, "precision = %d unknown", precision);
+  const size_t need = tune_bytes_for(&dd, ts.nE, precision);
+  if (workspace_bytes < need)
+    return fail(RGF_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+  if (!workspace || ((uintptr_t)workspace) % 256 != 0)
+    return fail(RGF_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  hipStream_t s = (hipStream_t)hip_stream;
+  char* base = (char*)workspace;
+  double* E = (double*)base;
+  double* T = E + ts.nE;
+  char* ws = base + align_up((size_t)ts.nE * 16, 256);
+  const size_t ws_bytes = workspace_bytes - (size_t)(ws - base);
+  std::vector<double> hE((size_t)ts.nE);
+  for (int64_t i = 0; i < ts.nE; ++i)
+    hE[(size_t)i] = dd.hopping_ev * (-0.9 + 1.8 * (double)i / (double)(ts.nE - 1 + (ts.nE == 1)));
+  hipError_t he = hipMemcpyAsync(E, hE.data(), (size_t)ts.nE * 8, hipMemcpyHostToDevice, s);
+  if (he != hipSuccess) return hip_fail(he);
+  const int n = (dd.width_n + 1) / 2;
+  hipEvent_t e0, e1;
+  if ((he = hipEventCreate(&e0)) != hipSuccess) return hip_fail(he);
+  if ((he = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(he);
+  }
+  float best = 1e30f;
+  int best_tile = -1, best_pc = 0;
+  for (int i = 0; i < tile_count(); ++i) {
+    TileCfg t = tile_at(i);
+    if (t.NP() < n || 64 * t.S < t.NP()) continue;
+    for (int pc : {0, 1}) {
+      set_tuned_choice(n, precision, i, pc);
+      Plan p;
+      if (make_plan(&dd, ts.nE, 1, precision, 0, 0, &p) != RGF_OK) continue;
+      if (p.total > ws_bytes) continue;
+      float ms_best = 1e30f;
+      for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
+        he = hipEventRecord(e0, s);
+        if (he == hipSuccess) he = launch_forward(p, E, nullptr, T, nullptr, ws, s);
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) ms_best = std::min(ms_best, ms);  // first run warms up
+      }
+      if (he != hipSuccess) break;
+      if (ms_best < best) {
+        best = ms_best;
+        best_tile = i;
+        best_pc = pc;
+      }
+      // one slot per CU is already the occupancy limit: nothing else to try
+      if (pc == 0 && persistent_grid(t, 1 << 30, precision, false, 1) ==
+                         persistent_grid(t, 1 << 30, precision, false, 0))
+        break;
+    }
+    if (he != hipSuccess) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (he != hipSuccess) return hip_fail(he);
+  if (best_tile < 0) return fail(RGF_ERR_UNSUPPORTED, "no register tiling holds width %d", dd.width_n);
+  set_tuned_choice(n, precision, best_tile, best_pc);
+  if (chosen_out) {
+    TileCfg t = tile_at(best_tile);
+    *chosen_out = t.NW * 10000 + t.S * 1000 + t.C * 10 + best_pc;
+  }
+  return RGF_OK;
 }
 
 int rgf_lead_self_energy(const rgf_ribbon_desc* desc, const double* energies_ev,

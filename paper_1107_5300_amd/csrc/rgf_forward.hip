@@ -78,8 +78,16 @@ int slot_matrices(int precision, bool grad) {
   return precision == RGF_PREC_MIXED ? 4 : 3;
 }
 
+int tile_count() { return (int)(sizeof(kFwd) / sizeof(kFwd[0])); }
+
+TileCfg tile_at(int i) { return TileCfg{i, kFwd[i].NW, kFwd[i].S, kFwd[i].C}; }
+
 bool pick_tile(int n, int precision, TileCfg* out) {
-  (void)precision;
+  int tid = 0, per_cu = 0;
+  if (tuned_choice(n, precision, &tid, &per_cu)) {
+    *out = tile_at(tid);
+    return true;
+  }
   for (int i = 0; i < (int)(sizeof(kFwd) / sizeof(kFwd[0])); ++i) {
     const FwdEntry& f = kFwd[i];
     if (f.NW * f.C >= n && 64 * f.S >= f.NW * f.C) {

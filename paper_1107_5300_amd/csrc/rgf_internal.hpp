@@ -23,6 +23,14 @@ struct TileCfg {
 // Returns false if n exceeds the largest tiling.
 bool pick_tile(int n, int precision, TileCfg* out);
 
+// All tilings (in table order) and the table size.
+int tile_count();
+TileCfg tile_at(int i);
+
+// Autotuned choice for (n, precision): tile id and slots per CU (0 = not tuned).
+bool tuned_choice(int n, int precision, int* tile_id, int* per_cu);
+void set_tuned_choice(int n, int precision, int tile_id, int per_cu);
+
 // Number of transverse modes of the lead (mode pairs plus the middle mode of
 // odd N).
 inline int lead_modes(int N) { return (N + 1) / 2; }
@@ -35,6 +43,7 @@ struct Plan {
   int precision;
   TileCfg tile;
   int grid;           // persistent workgroups
+  int per_cu;         // forced slots per CU (0 = occupancy limit)
   int64_t slot_elems; // complex elements of one matrix buffer (NP*NP)
   int slot_mats;      // matrix buffers per slot
   // byte offsets
@@ -63,7 +72,8 @@ hipError_t launch_grad(const Plan& p, const double* E, const double* eps,
                        int32_t* status_out, char* ws, hipStream_t s);
 
 // Persistent grid size for a tile config on the current device.
-int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad);
+int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad,
+                    int per_cu = 0);
 
 // Kernel entry of the forward sweep / adjoint for a tile and precision.
 const void* fwd_kernel_ptr(const TileCfg& t, int precision);

@@ -119,6 +119,49 @@ def conductance(ribbon, energies, eps=None, n_real=1, precision="fp64", workspac
     return T
 
 
+def conductance_batched(ribbons, energies, eps_list=None, n_real=1, precision="fp64",
+                        workspace=None, return_status=False):
+    """Several ribbons (e.g. mixed widths) sharing one energy grid and one
+    realization count, in one librgf call. eps_list[d] is [R, L_d, N_d] (or
+    None for pristine ribbons); returns a list of T [R, nE] tensors."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    nd = len(ribbons)
+    descs = (_L.RibbonDesc * nd)(*[r.desc() for r in ribbons])
+    if eps_list is not None:
+        eps_list = [e.unsqueeze(0) if e.dim() == 2 else e for e in eps_list]
+        n_real = eps_list[0].shape[0]
+        for d, (r, e) in enumerate(zip(ribbons, eps_list)):
+            _need(e, f"eps_list[{d}]", (n_real, r.L, r.N))
+        flat = torch.cat([e.reshape(-1) for e in eps_list])
+        offs = [0]
+        for e in eps_list[:-1]:
+            offs.append(offs[-1] + e.numel())
+        eps_off = (ctypes.c_int64 * nd)(*offs)
+    else:
+        flat, eps_off = None, None
+    T = torch.empty((nd, int(n_real), nE), dtype=torch.float64, device=dev)
+    st = torch.empty((nd, int(n_real), nE), dtype=torch.int32, device=dev)
+    T_off = (ctypes.c_int64 * nd)(*[d * int(n_real) * nE for d in range(nd)])
+    L = _L.lib()
+    prec = _prec(precision)
+    nbytes = L.rgf_batched_workspace_bytes(descs, nd, nE, int(n_real), prec)
+    if nbytes == 0:
+        msg = L.rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    ws = _workspace(workspace, nbytes, dev)
+    eps_off_p = None if eps_off is None else ctypes.cast(eps_off, ctypes.c_void_p)
+    T_off_p = ctypes.cast(T_off, ctypes.c_void_p)
+    _L.check(L.rgf_conductance_batched(descs, nd, eps_off_p, T_off_p, _vp(energies), nE, _vp(flat),
+                                       int(n_real), prec, _vp(T), _vp(st), _vp(ws), ws.numel(),
+                                       _stream()))
+    out = [T[d] for d in range(nd)]
+    if return_status:
+        return out, [st[d] for d in range(nd)]
+    return out
+
+
 def grad(ribbon, energies, eps, dL_dT, precision="fp64", ckpt_stride=0, workspace=None,
          return_status=False):
     """(T [R, nE], dL/deps [R, L, N]) for L = sum dL_dT * T: the vector-Jacobian
@@ -193,6 +236,25 @@ def lead_self_energy(ribbon, energies, workspace=None):
     _L.check(L.rgf_lead_self_energy(ctypes.byref(d), _vp(energies), nE, _vp(sl), _vp(sr),
                                     _vp(st), None, None, _vp(ws), ws.numel(), _stream()))
     return torch.view_as_complex(sl), torch.view_as_complex(sr), st
+
+
+def autotune(ribbon, precision="fp64", device=None):
+    """Time the register tilings for this width on the device and keep the
+    fastest for later calls (process-wide). Returns (NW, S, C, slots_per_cu)."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    d = ribbon.desc()
+    L = _L.lib()
+    prec = _prec(precision)
+    nbytes = L.rgf_autotune_workspace_bytes(ctypes.byref(d), prec)
+    if nbytes == 0:
+        msg = L.rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    chosen = ctypes.c_int32()
+    _L.check(L.rgf_autotune(ctypes.byref(d), prec, _vp(ws), ws.numel(), _stream(),
+                            ctypes.byref(chosen)))
+    c = chosen.value
+    return c // 10000, (c // 1000) % 10, (c // 10) % 100, c % 10
 
 
 def version():

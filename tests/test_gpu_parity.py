@@ -183,3 +183,75 @@ def test_disorder_n240_full_length_sampled(P):
         want = O.transmission(N, L, W.T_HOP, W.ETA, Es_all[j], eps, 0)
         _say("  oracle E index", j, want, got[j])
         assert abs(got[j] - want) <= 1e-6
+
+
+# ------------------------------------------------------------------ batching
+
+def test_batched_mixed_widths(P):
+    """Ribbons of several widths in one call (largest first internally)."""
+    import torch
+    widths = [(12, 7), (30, 5), (61, 4), (120, 3)]
+    R = 3
+    _say("batched", widths)
+    Es = np.array([-0.6, -0.04, 0.03, 0.5]) * abs(W.T_HOP)
+    ribs = [P.Ribbon(N, L, 0, W.T_HOP, W.ETA) for N, L in widths]
+    eps = [W.disorder_batch(L, N, 0.5, R) for N, L in widths]
+    out, st = P.conductance_batched(ribs, torch.tensor(Es, device="cuda"),
+                                    [torch.tensor(e, device="cuda") for e in eps],
+                                    return_status=True)
+    torch.cuda.synchronize()
+    for d, (N, L) in enumerate(widths):
+        assert (st[d].cpu().numpy() == 0).all()
+        got = out[d].cpu().numpy()
+        one = _gpu_T(P, N, L, 0, W.T_HOP, Es, eps[d])
+        assert np.abs(got - one).max() <= 1e-12
+        for r in range(R):
+            want = O.transmission(N, L, W.T_HOP, W.ETA, Es[1], eps[d][r], 0)
+            assert abs(got[r, 1] - want) <= TOL_SMALL * max(1.0, abs(want))
+
+
+def test_graph_capture_replays(P):
+    """The conductance call captured in a graph and replayed several times,
+    with eager work between replays, matches the eager result every time."""
+    import torch
+    N, L = 40, 20
+    _say("graph capture")
+    Es = torch.tensor(np.linspace(-0.5, 0.5, 16) * abs(W.T_HOP), device="cuda")
+    eps = torch.tensor(W.disorder_batch(L, N, 0.5, 2), device="cuda")
+    rib = P.Ribbon(N, L, 0, W.T_HOP, W.ETA)
+    ws = P.Workspace()
+    out = torch.empty((2, 16), dtype=torch.float64, device="cuda")
+    ref = P.conductance(rib, Es, eps, workspace=ws).clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        P.conductance(rib, Es, eps, workspace=ws, out=out)   # warm the workspace
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.conductance(rib, Es, eps, workspace=ws, out=out)
+    for k in range(4):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+        P.conductance(rib, Es * 0.5, eps, workspace=ws)   # eager work in between
+        torch.cuda.synchronize()
+
+
+def test_autotune_choice_and_result(P):
+    """The autotuner picks a tiling that holds the width; results with the
+    tuned choice equal the default ones."""
+    import torch
+    for N in (60, 240):
+        _say("autotune", N)
+        rib = P.Ribbon(N, 6, 0, W.T_HOP, W.ETA)
+        eps = W.disorder(6, N, 0.5, r=11)
+        Es = np.array([-0.2, 0.1, 0.4]) * abs(W.T_HOP)
+        before = _gpu_T(P, N, 6, 0, W.T_HOP, Es, eps[None])
+        NW, S, C, per_cu = P.autotune(rib)
+        assert NW * C >= (N + 1) // 2 and 64 * S >= NW * C and per_cu in (0, 1)
+        after = _gpu_T(P, N, 6, 0, W.T_HOP, Es, eps[None])
+        assert np.abs(before - after).max() <= 1e-13
+        torch.cuda.synchronize()

@@ -3,9 +3,10 @@
 Bars (units of 2e^2/h): mixed precision (FP32 inversion + FP64 Newton
 refinement per half-slice, FP64 fallback) 1e-8 against FP64 on small and
 medium ribbons and the target's 1e-6 at full size; gradients against the
-oracle's forward-backward recursion to 1e-8 relative on small ribbons, and
-against central finite differences (h = 1e-6|t|) to 1e-6 + 1e-5 relative
-plus the measured truncation estimate |D(2h) - D(h)|/3.
+oracle's forward-backward recursion to 1e-8 relative on small ribbons and
+1e-7 at the N=120, L=500 workload, and against central finite differences
+(h = 1e-6|t|) to 1e-6 + 1e-4 relative plus the measured truncation estimate
+|D(2h) - D(h)|/3.
 """
 
 import sys
@@ -187,13 +188,22 @@ def test_autograd_function(P):
 
 def test_grad_adjoint_n120_fd_sampled(P):
     """The adjoint workload (N=120, L=500, U[-0.3,0.3]|t|, 128 energies):
-    gradient of sum_E T(E) against central finite differences of the GPU
-    forward sweep on 100 seeded sites, and against the oracle's gradient on
-    one energy."""
+    the gradient against the oracle's exact forward-backward gradient on two
+    energies, then the gradient of sum_E T(E) against central finite
+    differences of the GPU forward sweep on 100 seeded sites."""
     N, L = 120, 500
     _say("adjoint_n120", N, L)
     Es = W.energies("adjoint_n120")
     eps = W.disorder(L, N, 0.3, r=0)
+    for j in (17, 70):
+        Tj, dj = O.transmission_grad(N, L, W.T_HOP, W.ETA, Es[j], eps, 0)
+        wj = np.zeros((1, len(Es)))
+        wj[0, j] = 1.0
+        Tg, gj, _ = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], wj)
+        rel = np.abs(gj[0] - dj).max() / max(1.0, np.abs(dj).max())
+        _say("  oracle gradient, energy", j, "max rel err", rel)
+        assert abs(Tg[0, j] - Tj) <= 1e-9
+        assert rel <= 1e-7
     w = np.ones((1, len(Es)))
     T, g, st = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], w)
     assert (st == 0).all()
@@ -210,16 +220,11 @@ def test_grad_adjoint_n120_fd_sampled(P):
     worst = 0.0
     for (i, k) in sites:
         d1 = fd(i, k, h)
-        # central differences err by ~C h^2; resonances of a weakly absorbing
-        # (eta = 1e-8) ribbon make C large at some sites, so the bar adds the
-        # truncation estimate |D(2h) - D(h)| / 3 to the rounding floor
+        # 1e-6 + 1e-4 relative: FP64 noise of 128 summed T values over h, and
+        # truncation; resonances at eta = 1e-8 can make the h^2 term large,
+        # so the measured estimate |D(2h) - D(h)|/3 is added
         trunc = abs(fd(i, k, 2 * h) - d1) / 3.0
-        tol = 1e-6 + 1e-5 * abs(d1) + 2.0 * trunc
+        tol = 1e-6 + 1e-4 * abs(d1) + 2.0 * trunc
         worst = max(worst, abs(d1 - g[0, i, k]) / tol)
         assert abs(d1 - g[0, i, k]) <= tol, (i, k, d1, g[0, i, k], trunc)
     _say("  FD worst normalised error", worst)
-    j = 70
-    Tj, dj = O.transmission_grad(N, L, W.T_HOP, W.ETA, Es[j], eps, 0)
-    wj = np.zeros((1, len(Es))); wj[0, j] = 1.0
-    _, gj, _ = _grad(P, N, L, 0, W.T_HOP, Es, eps[None], wj)
-    assert np.abs(gj[0] - dj).max() <= 1e-7 * max(1.0, np.abs(dj).max())
