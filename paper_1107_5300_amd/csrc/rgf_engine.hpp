@@ -27,11 +27,14 @@ __device__ __forceinline__ void wave_sync_lds() {
 // derived from a loop-invariant, wave-uniform pointer is not hoisted out of
 // the slice loop (hoisted per-lane addresses would occupy dozens of VGPRs
 // for the whole sweep).
+// The pointer must be wave-uniform; it is moved to SGPRs first.
 template <typename P>
 __device__ __forceinline__ P* opaque_uniform(P* p) {
-  uint64_t v = reinterpret_cast<uint64_t>(p);
-  asm volatile("" : "+s"(v));
-  return reinterpret_cast<P*>(v);
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
 }
 
 template <typename T, int S, int C>
@@ -52,20 +55,24 @@ __device__ __forceinline__ void zero_regs(cx<T> (&A)[S][C]) {
 // X = P^T A^{-1} P^T for the row permutation P that maps step k to row p_k:
 // A^{-1}[i][j] = X[p_i][q_j] with q the inverse permutation (q_{p_k} = k).
 //
-// One barrier per step: the wave owning column k+1 searches its pivot right
-// after updating, and publishes the column and the pivot row index through a
-// double-buffered LDS column. The pivot row itself is broadcast inside each
-// wave through that wave's LDS scratch.
+// The step is written as one update with no per-element selection:
+//   A[r][c] -= m'_r * v_c,   v_c = A[p][c] (c != k), v_k = 1,
+//   m'_r = A[r][k] / A[p][k] (r != p),  m'_p = 1 - 1/A[p][k],
+// after column k is reset to the unit vector e_p. This yields the scaled
+// pivot row in row p, the eliminated rows elsewhere, and the inverse's column
+// (-A[r][k]/piv, 1/piv at p) in column k.
 //
-// LDS: colbuf[2][NP] (T), wbuf[NW][NP] (T), pivrow[NP], pinv[NP] (int),
-// flag (int; set to 1 on an exact zero pivot).
+// One barrier per step: the wave owning column k+1 selects its pivot right
+// after updating, computes 1/pivot, and publishes the column, the pivot row
+// index and 1/pivot through double-buffered LDS. The raw pivot row of each
+// wave's columns is broadcast inside the wave through its LDS scratch.
+//
+// LDS: colbuf[2][NP] (T), ipivbuf[2] (T), wbuf[NW][NP] (T), pivrow[NP],
+// pinv[NP] (int), flag (int; set to 1 on an exact zero pivot).
 // ----------------------------------------------------------------------------
-// Pivot search on column kc held in register column J of the calling wave
-// (compile-time J, so the tile stays in registers): argmax over unused rows
-// < n, published with the column through the double-buffered LDS column.
 template <typename T, int NW, int S, int C, int J>
 __device__ __forceinline__ void gj_pivot_publish(const cx<T> (&A)[S][C], int kc, int n,
-                                                 uint32_t used, cx<T>* colbuf,
+                                                 uint32_t used, cx<T>* colbuf, cx<T>* ipivbuf,
                                                  int* pivrow, int* flag) {
   constexpr int NP = NW * C;
   const int lane = lane_id();
@@ -101,8 +108,12 @@ __device__ __forceinline__ void gj_pivot_publish(const cx<T> (&A)[S][C], int kc,
     const int r = lane + 64 * s;
     if (r < NP) cb[r] = A[s][J];
   }
+  // the pivot value is read back from the published column (LDS requests of
+  // one wave complete in order)
+  wave_sync_lds();
   if (lane == 0) {
     pivrow[kc] = bidx;
+    ipivbuf[kc & 1] = crcp(cb[min(bidx, NP - 1)]);
     if (!(best > T(0))) *flag = 1;
   }
 }
@@ -111,12 +122,27 @@ __device__ __forceinline__ void gj_pivot_publish(const cx<T> (&A)[S][C], int kc,
 template <typename T, int NW, int S, int C, int J = 0>
 __device__ __forceinline__ void gj_pivot_dispatch(const cx<T> (&A)[S][C], int kc, int n,
                                                   uint32_t used, cx<T>* colbuf,
-                                                  int* pivrow, int* flag) {
+                                                  cx<T>* ipivbuf, int* pivrow, int* flag) {
   if constexpr (J < C) {
     if (wave_id() * C + J == kc)
-      gj_pivot_publish<T, NW, S, C, J>(A, kc, n, used, colbuf, pivrow, flag);
+      gj_pivot_publish<T, NW, S, C, J>(A, kc, n, used, colbuf, ipivbuf, pivrow, flag);
     else
-      gj_pivot_dispatch<T, NW, S, C, J + 1>(A, kc, n, used, colbuf, pivrow, flag);
+      gj_pivot_dispatch<T, NW, S, C, J + 1>(A, kc, n, used, colbuf, ipivbuf, pivrow, flag);
+  }
+}
+
+// Column k := e_p in the register column that holds it (if this wave owns it).
+template <typename T, int NW, int S, int C, int J = 0>
+__device__ __forceinline__ void gj_unit_column(cx<T> (&A)[S][C], int k, int pk) {
+  if constexpr (J < C) {
+    if (wave_id() * C + J == k) {
+      const int lane = lane_id();
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        A[s][J] = mk<T>((lane + 64 * s == pk) ? T(1) : T(0), T(0));
+    } else {
+      gj_unit_column<T, NW, S, C, J + 1>(A, k, pk);
+    }
   }
 }
 
@@ -128,50 +154,45 @@ __device__ __forceinline__ void gj_invert(cx<T> (&A)[S][C], int n, cx<T>* colbuf
   constexpr int NT = NW * 64;
   const int lane = lane_id(), w = wave_id();
   cx<T>* wbuf = wbuf_all + w * NP;
+  cx<T>* ipivbuf = colbuf + 2 * NP;
   uint32_t used = 0;
-  if (n > 0 && w == 0) gj_pivot_dispatch<T, NW, S, C>(A, 0, n, used, colbuf, pivrow, flag);
+  if (n > 0 && w == 0)
+    gj_pivot_dispatch<T, NW, S, C>(A, 0, n, used, colbuf, ipivbuf, pivrow, flag);
   for (int k = 0; k < n; ++k) {
     __syncthreads();
     const cx<T>* cb = colbuf + (k & 1) * NP;
     const int pk = min(max(pivrow[k], 0), NP - 1);
     const int pl = pk & 63, ps = pk >> 6;
-    const cx<T> ipiv = crcp(cb[pk]);
+    const cx<T> ipiv = ipivbuf[k & 1];
     cx<T> m[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int r = lane + 64 * s;
-      m[s] = (r < NP) ? cb[r] : mk<T>(T(0), T(0));
+      const cx<T> a = (r < NP) ? cb[r] : mk<T>(T(0), T(0));
+      m[s] = (r == pk) ? mk<T>(T(1) - ipiv.re, -ipiv.im) : cmul(a, ipiv);
     }
-    // broadcast the scaled pivot row (row p_k / pivot; 1/pivot in column k)
-    // of this wave's columns
+    // raw pivot row of this wave's columns, with 1 in column k: the pivot
+    // lane writes all S of its rows (constant register indices keep the tile
+    // in registers); the readers pick slot ps by LDS address
     if (lane == pl) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (s == ps) {
+      for (int s = 0; s < S; ++s)
 #pragma unroll
-          for (int j = 0; j < C; ++j)
-            wbuf[j] = (w * C + j == k) ? ipiv : cmul(A[s][j], ipiv);
-        }
-      }
+        for (int j = 0; j < C; ++j) wbuf[s * C + j] = A[s][j];
       used |= 1u << ps;
     }
+    if (lane == 0 && w == k / C) wbuf[ps * C + k - w * C] = mk<T>(T(1), T(0));
     wave_sync_lds();
+    gj_unit_column<T, NW, S, C>(A, k, pk);
+    const cx<T>* prow = wbuf + ps * C;
 #pragma unroll
     for (int j = 0; j < C; ++j) {
-      const int c = w * C + j;
-      const bool is_k = (c == k);
-      const cx<T> rj = wbuf[j];
+      const cx<T> v = prow[j];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int r = lane + 64 * s;
-        const bool is_p = (r == pk);
-        cx<T> old = A[s][j];
-        if (is_k) old = mk<T>(is_p ? T(1) : T(0), T(0));
-        A[s][j] = is_p ? rj : cfms(m[s], rj, old);
-      }
+      for (int s = 0; s < S; ++s) A[s][j] = cfms(m[s], v, A[s][j]);
     }
     if (k + 1 < n && w == (k + 1) / C)
-      gj_pivot_dispatch<T, NW, S, C>(A, k + 1, n, used, colbuf, pivrow, flag);
+      gj_pivot_dispatch<T, NW, S, C>(A, k + 1, n, used, colbuf, ipivbuf, pivrow, flag);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += NT) pinv[pivrow[i]] = i;

@@ -56,7 +56,7 @@ struct SweepArgs {
 template <int NW, int S, int C>
 struct SweepSmem {
   static constexpr int NP = NW * C;
-  cx<double> colbuf[2 * NP];   // also used as cx<float>[4*NP]
+  cx<double> colbuf[2 * NP + 2];   // + 1/pivot x 2; also used as cx<float>
   cx<double> wbuf[NW * NP];    // also used as cx<float>[2*NW*NP]
   cx<double> As[KC * NP];
   cx<double> Bs[KC * NP];
