@@ -219,18 +219,19 @@ def main():
         "cpu_baseline": None if cpu is None else {
             k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
         "accuracy": {
-            "max_abs_dT_vs_oracle": r["dT"],
+            "max_abs_dT_vs_oracle": None if r["dT"] is None else float(r["dT"]),
             "oracle_energies": sorted(oracle_T.keys()),
             "bar": ACC_TOL,
-            "meets_bar": (r["dT"] is not None and r["dT"] <= ACC_TOL),
+            "meets_bar": bool(r["dT"] is not None and r["dT"] <= ACC_TOL),
             "tuples_not_ok": int((r["st"] != 0).sum()),
         },
         "rates": {p: {"slice_steps_per_s": steps_per_call * K / results[p]["wall"],
-                      "max_abs_dT_vs_oracle": results[p]["dT"],
+                      "max_abs_dT_vs_oracle": (None if results[p]["dT"] is None
+                                               else float(results[p]["dT"])),
                       "max_abs_dT_vs_fp64_all_energies": results[p].get("dT_vs_fp64_all"),
                       "tile": results[p]["tile"]} for p in results},
     }
-    print(json.dumps(line), flush=True)
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)), flush=True)
 
 
 if __name__ == "__main__":
