@@ -15,7 +15,9 @@
 namespace rgf {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: lets the compiler branch on it
+}
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -56,93 +58,185 @@ __device__ __forceinline__ void zero_regs(cx<T> (&A)[S][C]) {
 // A^{-1}[i][j] = X[p_i][q_j] with q the inverse permutation (q_{p_k} = k).
 //
 // The step is written as one update with no per-element selection:
-//   A[r][c] -= m'_r * v_c,   v_c = A[p][c] (c != k), v_k = 1,
-//   m'_r = A[r][k] / A[p][k] (r != p),  m'_p = 1 - 1/A[p][k],
-// after column k is reset to the unit vector e_p. This yields the scaled
-// pivot row in row p, the eliminated rows elsewhere, and the inverse's column
-// (-A[r][k]/piv, 1/piv at p) in column k.
+//   A[r][c] -= m'_r * v_c,   v_c = A[p][c] (c != k),  v_k = A[p][k] + 1,
+//   m'_r = A[r][k] / A[p][k] (r != p),  m'_p = 1 - 1/A[p][k].
+// For c != k this is the elimination (rows r != p) and the scaling of the
+// pivot row (row p). For column k it yields -A[r][k]/A[p][k] in rows r != p
+// and 1/A[p][k] in row p, the inverse's column, so column k needs no reset.
+// The constant 1 in m'_p and v_k makes the rounding error grow with |pivot|
+// (relative to the result); the caller scales the matrix to entries of
+// magnitude below 1 (an exact power of two) to keep the error at the level
+// of the elimination itself.
 //
-// One barrier per step: the wave owning column k+1 selects its pivot right
-// after updating, computes 1/pivot, and publishes the column, the pivot row
-// index and 1/pivot through double-buffered LDS. The raw pivot row of each
-// wave's columns is broadcast inside the wave through its LDS scratch.
+// The k loop runs as a runtime loop over wave blocks (k = kb*C + J) around
+// compile-time steps J, so every register access has a constant index. One
+// barrier per step; the wave that owns column k+1 updates that column first,
+// then selects its pivot (a packed 32-bit key reduced across the wave by
+// DPP, no LDS round trip), publishes the column, the pivot row and 1/pivot
+// through double-buffered LDS, and updates its other columns while the
+// other waves do theirs. The raw pivot row of each wave's columns (pivot + 1
+// in column k) is broadcast inside the wave through its LDS scratch.
 //
-// LDS: colbuf[2][NP] (T), ipivbuf[2] (T), wbuf[NW][NP] (T), pivrow[NP],
-// pinv[NP] (int), flag (int; set to 1 on an exact zero pivot).
+// LDS: colbuf[2][NP + 1] (T: the column, then 1/pivot), wbuf[NW][NP] (T;
+// the first C entries per wave here), pivrow[NP], pinv[NP] (int), flag (int;
+// set to 1 on an exact zero pivot).
 // ----------------------------------------------------------------------------
+// Wave-wide maximum of a 32-bit key by DPP (no LDS traffic); every lane
+// gets the result.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false)); // row_half_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false)); // row_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false)); // row_bcast:15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false)); // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Pivot key of row r: the magnitude |re|+|im| rounded to float with its
+// low 8 bits replaced by 255 - r, so the largest key is the largest
+// magnitude (to a relative 2^-15, ample for partial pivoting) and, among
+// equal magnitudes, the lowest row. Unusable rows get 0; usable rows with a
+// zero (or NaN) magnitude still get 255 - r > 0, so the choice stays a valid,
+// unused row.
+template <typename T>
+__device__ __forceinline__ uint32_t pivot_key(cx<T> v, int r, bool usable) {
+  if (!usable) return 0u;
+  float m = (float)cabs1(v);
+  if (!(m >= 0.0f)) m = 0.0f;
+  return (__float_as_uint(m) & 0xFFFFFF00u) | (uint32_t)(255 - r);
+}
+
+// Register column J of slot s (s uniform or not; a chain of selects over the
+// S slots, with constant register indices).
+template <typename T, int S, int C, int J>
+__device__ __forceinline__ cx<T> pick_slot(const cx<T> (&A)[S][C], int s) {
+  cx<T> v = A[0][J];
+#pragma unroll
+  for (int i = 1; i < S; ++i)
+    if (s == i) v = A[i][J];
+  return v;
+}
+
+// A[s][J] -= m[s] * v  for one register column.
+template <typename T, int S, int C, int J>
+__device__ __forceinline__ void gj_update_column(cx<T> (&A)[S][C], const cx<T> (&m)[S],
+                                                 cx<T> v) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) A[s][J] = cfms(m[s], v, A[s][J]);
+}
+
+template <typename T, int S, int C, int J, int SKIP>
+__device__ __forceinline__ void gj_update_rest(cx<T> (&A)[S][C], const cx<T> (&m)[S],
+                                               const cx<T> (&v)[C]) {
+  if constexpr (J < C) {
+    if constexpr (J != SKIP) gj_update_column<T, S, C, J>(A, m, v[J]);
+    gj_update_rest<T, S, C, J + 1, SKIP>(A, m, v);
+  }
+}
+
+// wbuf[j] = A[ps][j] for the C register columns (ps uniform). The empty
+// asm statement, distinct per slot, keeps the optimiser from merging the
+// branches into one store of a dynamically indexed register (which would
+// move the whole tile to scratch memory).
+template <typename T, int S, int C, int SS>
+__device__ __forceinline__ void gj_write_row(const cx<T> (&A)[S][C], int ps, cx<T>* wbuf) {
+  if constexpr (SS < S) {
+    if (ps == SS) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) wbuf[j] = A[SS][j];
+      asm volatile("; gj row slot %0" ::"n"(SS));
+    } else {
+      gj_write_row<T, S, C, SS + 1>(A, ps, wbuf);
+    }
+  }
+}
+
+// Pivot selection for column kc, held in register column J of the calling
+// (owner) wave: publishes the column, the pivot row and 1/pivot.
 template <typename T, int NW, int S, int C, int J>
-__device__ __forceinline__ void gj_pivot_publish(const cx<T> (&A)[S][C], int kc, int n,
-                                                 uint32_t used, cx<T>* colbuf, cx<T>* ipivbuf,
-                                                 int* pivrow, int* flag) {
+__device__ __forceinline__ void gj_select_pivot(const cx<T> (&A)[S][C], int kc, int n,
+                                                uint32_t used, cx<T>* colbuf, int* pivrow,
+                                                int* flag) {
   constexpr int NP = NW * C;
   const int lane = lane_id();
-  T best = T(-1);
-  int bidx = 0x7fffffff;
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int r = lane + 64 * s;
-    // NaN magnitudes count as 0 so an unused row always wins over -1 and
-    // the pivot index stays inside [0, n)
-    T mag = T(-1);
-    if (r < n && !((used >> s) & 1u)) {
-      mag = cabs1(A[s][J]);
-      if (!(mag >= T(0))) mag = T(0);
-    }
-    if (mag > best) {
-      best = mag;
-      bidx = r;
-    }
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    T ob = __shfl_xor(best, off);
-    int oi = __shfl_xor(bidx, off);
-    if (ob > best || (ob == best && oi < bidx)) {
-      best = ob;
-      bidx = oi;
-    }
-  }
-  cx<T>* cb = colbuf + (kc & 1) * NP;
+  cx<T>* cb = colbuf + (kc & 1) * (NP + 1);
+  uint32_t key = 0u;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int r = lane + 64 * s;
     if (r < NP) cb[r] = A[s][J];
+    key = max(key, pivot_key(A[s][J], r, r < n && !((used >> s) & 1u)));
   }
-  // the pivot value is read back from the published column (LDS requests of
-  // one wave complete in order)
-  wave_sync_lds();
-  if (lane == 0) {
-    pivrow[kc] = bidx;
-    ipivbuf[kc & 1] = crcp(cb[min(bidx, NP - 1)]);
-    if (!(best > T(0))) *flag = 1;
-  }
-}
-
-// Calls gj_pivot_publish for the register column that holds column kc.
-template <typename T, int NW, int S, int C, int J = 0>
-__device__ __forceinline__ void gj_pivot_dispatch(const cx<T> (&A)[S][C], int kc, int n,
-                                                  uint32_t used, cx<T>* colbuf,
-                                                  cx<T>* ipivbuf, int* pivrow, int* flag) {
-  if constexpr (J < C) {
-    if (wave_id() * C + J == kc)
-      gj_pivot_publish<T, NW, S, C, J>(A, kc, n, used, colbuf, ipivbuf, pivrow, flag);
-    else
-      gj_pivot_dispatch<T, NW, S, C, J + 1>(A, kc, n, used, colbuf, ipivbuf, pivrow, flag);
+  key = wave_max_u32(key);
+  const int pk = min(255 - (int)(key & 0xFFu), NP - 1);
+  if (lane == (pk & 63)) {
+    const cx<T> pv = pick_slot<T, S, C, J>(A, pk >> 6);
+    pivrow[kc] = pk;
+    cb[NP] = crcp(pv);
+    if (!(cabs1(pv) > T(0))) *flag = 1;
   }
 }
 
-// Column k := e_p in the register column that holds it (if this wave owns it).
-template <typename T, int NW, int S, int C, int J = 0>
-__device__ __forceinline__ void gj_unit_column(cx<T> (&A)[S][C], int k, int pk) {
-  if constexpr (J < C) {
-    if (wave_id() * C + J == k) {
-      const int lane = lane_id();
+// Elimination step k = kb*C + J (J compile-time).
+template <typename T, int NW, int S, int C, int J>
+__device__ __forceinline__ void gj_step(cx<T> (&A)[S][C], int kb, int n, uint32_t& used,
+                                        cx<T>* colbuf, cx<T>* wbuf, int* pivrow, int* flag) {
+  constexpr int NP = NW * C;
+  constexpr int JN = (J + 1) % C;  // register column of k + 1
+  const int lane = lane_id(), w = wave_id();
+  const int k = kb * C + J;
+  const int kbn = (J + 1 == C) ? kb + 1 : kb;  // owner wave of k + 1
+  __syncthreads();
+  // all LDS reads of the step's column in one round trip
+  const cx<T>* cb = colbuf + (k & 1) * (NP + 1);
+  const int pkr = pivrow[k];
+  const cx<T> ipiv = cb[NP];
+  cx<T> a[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s)
-        A[s][J] = mk<T>((lane + 64 * s == pk) ? T(1) : T(0), T(0));
-    } else {
-      gj_unit_column<T, NW, S, C, J + 1>(A, k, pk);
+  for (int s = 0; s < S; ++s) {
+    const int r = lane + 64 * s;
+    a[s] = (r < NP) ? cb[r] : mk<T>(T(0), T(0));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  const int pk = min(max(pkr, 0), NP - 1);
+  const int pl = pk & 63, ps = pk >> 6;
+  cx<T> m[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int r = lane + 64 * s;
+    m[s] = (r == pk) ? mk<T>(T(1) - ipiv.re, -ipiv.im) : cmul(a[s], ipiv);
+  }
+  // raw pivot row of this wave's columns, with pivot + 1 in column k,
+  // written by the pivot lane (slot ps is wave-uniform: one branch per slot
+  // keeps the register indices constant)
+  if (lane == pl) {
+    gj_write_row<T, S, C, 0>(A, ps, wbuf);
+    if (w == kb) {
+      const cx<T> pv = pick_slot<T, S, C, J>(A, ps);
+      wbuf[J] = mk<T>(pv.re + T(1), pv.im);
     }
+    used |= 1u << ps;
+  }
+  wave_sync_lds();
+  const cx<T>* prow = wbuf;
+  cx<T> v[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) v[j] = prow[j];
+  __builtin_amdgcn_sched_barrier(0);
+  gj_update_column<T, S, C, JN>(A, m, v[JN]);
+  if (w == kbn && k + 1 < n)
+    gj_select_pivot<T, NW, S, C, JN>(A, k + 1, n, used, colbuf, pivrow, flag);
+  gj_update_rest<T, S, C, 0, JN>(A, m, v);
+}
+
+template <typename T, int NW, int S, int C, int J>
+__device__ __forceinline__ void gj_block(cx<T> (&A)[S][C], int kb, int n, uint32_t& used,
+                                         cx<T>* colbuf, cx<T>* wbuf, int* pivrow, int* flag) {
+  if constexpr (J < C) {
+    if (kb * C + J >= n) return;
+    gj_step<T, NW, S, C, J>(A, kb, n, used, colbuf, wbuf, pivrow, flag);
+    gj_block<T, NW, S, C, J + 1>(A, kb, n, used, colbuf, wbuf, pivrow, flag);
   }
 }
 
@@ -152,60 +246,70 @@ __device__ __forceinline__ void gj_invert(cx<T> (&A)[S][C], int n, cx<T>* colbuf
                                           int* flag) {
   constexpr int NP = NW * C;
   constexpr int NT = NW * 64;
-  const int lane = lane_id(), w = wave_id();
+  const int w = wave_id();
   cx<T>* wbuf = wbuf_all + w * NP;
-  cx<T>* ipivbuf = colbuf + 2 * NP;
   uint32_t used = 0;
-  if (n > 0 && w == 0)
-    gj_pivot_dispatch<T, NW, S, C>(A, 0, n, used, colbuf, ipivbuf, pivrow, flag);
-  for (int k = 0; k < n; ++k) {
-    __syncthreads();
-    const cx<T>* cb = colbuf + (k & 1) * NP;
-    const int pk = min(max(pivrow[k], 0), NP - 1);
-    const int pl = pk & 63, ps = pk >> 6;
-    const cx<T> ipiv = ipivbuf[k & 1];
-    cx<T> m[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = lane + 64 * s;
-      const cx<T> a = (r < NP) ? cb[r] : mk<T>(T(0), T(0));
-      m[s] = (r == pk) ? mk<T>(T(1) - ipiv.re, -ipiv.im) : cmul(a, ipiv);
-    }
-    // raw pivot row of this wave's columns, with 1 in column k: the pivot
-    // lane writes all S of its rows (constant register indices keep the tile
-    // in registers); the readers pick slot ps by LDS address
-    if (lane == pl) {
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int j = 0; j < C; ++j) wbuf[s * C + j] = A[s][j];
-      used |= 1u << ps;
-    }
-    if (lane == 0 && w == k / C) wbuf[ps * C + k - w * C] = mk<T>(T(1), T(0));
-    wave_sync_lds();
-    gj_unit_column<T, NW, S, C>(A, k, pk);
-    const cx<T>* prow = wbuf + ps * C;
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const cx<T> v = prow[j];
-#pragma unroll
-      for (int s = 0; s < S; ++s) A[s][j] = cfms(m[s], v, A[s][j]);
-    }
-    if (k + 1 < n && w == (k + 1) / C)
-      gj_pivot_dispatch<T, NW, S, C>(A, k + 1, n, used, colbuf, ipivbuf, pivrow, flag);
+  if (n > 0 && w == 0) gj_select_pivot<T, NW, S, C, 0>(A, 0, n, used, colbuf, pivrow, flag);
+  for (int kb = 0; kb < NW; ++kb) {
+    if (kb * C >= n) break;
+    gj_block<T, NW, S, C, 0>(A, kb, n, used, colbuf, wbuf, pivrow, flag);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += NT) pinv[pivrow[i]] = i;
   __syncthreads();
 }
 
+// Scale factor for the inversion: 2^-e with the largest |re| + |im| of the
+// tile in [2^(e-1), 2^e), so the scaled entries lie below 1 (1 if the tile
+// holds a NaN or an infinity; a zero tile is left as it is). The maximum is
+// taken on the high 32 bits of the magnitudes (monotone for non-negative
+// floating-point numbers). Costs one barrier, which also orders the previous
+// users of the shared buffers before the inversion.
+__device__ __forceinline__ uint32_t mag_hi(double v) {
+  return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32);
+}
+__device__ __forceinline__ uint32_t mag_hi(float v) { return __float_as_uint(v); }
+
+template <typename T, int NW, int S, int C>
+__device__ __forceinline__ T tile_scale(const cx<T> (&A)[S][C], uint32_t* red) {
+  constexpr bool F64 = sizeof(T) == sizeof(double);
+  constexpr int MB = F64 ? 20 : 23;           // mantissa bits in the high word
+  constexpr uint32_t EMAX = F64 ? 0x7FFu : 0xFFu;
+  constexpr int BIAS = F64 ? 1023 : 127, EMIN = F64 ? -1022 : -126;
+  uint32_t b = 0u;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j = 0; j < C; ++j) b = max(b, mag_hi(cabs1(A[s][j])));
+  b = wave_max_u32(b);
+  if (lane_id() == 0) red[wave_id()] = b;
+  __syncthreads();
+  uint32_t m = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) m = max(m, red[i]);
+  const int ex = (int)((m >> MB) & EMAX);
+  if (m == 0u || ex == (int)EMAX) return T(1);
+  // max in [2^(ex-BIAS), 2^(ex-BIAS+1)) -> multiply by 2^(BIAS-1-ex)
+  // (a subnormal maximum, ex = 0, scales by 2^(BIAS-1))
+  return (T)ldexp(1.0, max(BIAS - 1 - ex, EMIN));
+}
+
+template <typename T, int S, int C>
+__device__ __forceinline__ void scale_regs(cx<T> (&A)[S][C], T f) {
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j = 0; j < C; ++j) A[s][j] = cscale(A[s][j], f);
+}
+
 // Write the inverse held (permuted) in registers to a column-major global
 // buffer K with leading dimension NP: K[i][j] = X[p_i][q_j]. Each wave takes
 // its columns c (target column p_c), un-permutes the rows through its LDS
 // scratch and stores whole columns coalesced. Columns/rows >= n are skipped.
-// If K2 is non-null the same matrix is also written there.
+// Every entry is multiplied by f (the scale of the inversion; a power of
+// two). If K2 is non-null the same matrix is also written there.
 template <typename T, typename TG, int NW, int S, int C>
-__device__ __forceinline__ void store_unpermuted(const cx<T> (&X)[S][C], int n,
+__device__ __forceinline__ void store_unpermuted(const cx<T> (&X)[S][C], int n, T f,
                                                  cx<T>* wbuf_all, const int* pivrow,
                                                  const int* pinv, cx<TG>* K,
                                                  cx<TG>* K2) {
@@ -230,7 +334,7 @@ __device__ __forceinline__ void store_unpermuted(const cx<T> (&X)[S][C], int n,
       const int r = lane + 64 * s;
       if (r < n) {
         cx<T> v = wbuf[r];
-        cx<TG> g = mk<TG>((TG)v.re, (TG)v.im);
+        cx<TG> g = mk<TG>((TG)(v.re * f), (TG)(v.im * f));
         stg(K + (size_t)col * NP + r, g);
         if (K2) stg(K2 + (size_t)col * NP + r, g);
       }
@@ -261,43 +365,77 @@ __device__ __forceinline__ void store_regs(const cx<T> (&X)[S][C], int nr, int n
 
 // ----------------------------------------------------------------------------
 // acc[r][c] = sum_{k < nk} fa(r, k) * fb(k, c) for the NP x NP register tile.
-// The accessors return zero outside the operand shapes. Operands are staged
-// KC columns of fa / KC rows of fb at a time through LDS (As[KC][NP],
-// Bs[KC][NP]); each lane reads its S rows of As and the wave's C columns of Bs
-// (a broadcast read), then issues S*C complex FMAs.
+// The accessors return zero outside the operand shapes. KC columns of fa and
+// KC rows of fb are staged through double-buffered LDS (As[2][KC][NP],
+// Bs[2][KC][NP]): the global loads of chunk c+1 are issued before the FMAs
+// of chunk c and written to the other buffer afterwards, so one barrier per
+// chunk suffices. Each lane reads its S rows of As and the wave's C columns
+// of Bs (a broadcast read), then issues S*C complex FMAs.
 // ----------------------------------------------------------------------------
 template <typename TA, int NW, int S, int C, int KC, class FA, class FB>
 __device__ __forceinline__ void gemm_regs(cx<TA> (&acc)[S][C], int nk, FA fa, FB fb,
                                           cx<TA>* As, cx<TA>* Bs) {
   constexpr int NP = NW * C;
   constexpr int NT = NW * 64;
+  constexpr int CH = KC * NP;
+  constexpr int PER = (CH + NT - 1) / NT;
   const int lane = lane_id(), w = wave_id();
   zero_regs(acc);
-  for (int k0 = 0; k0 < nk; k0 += KC) {
-    for (int idx = threadIdx.x; idx < KC * NP; idx += NT) {
-      const int kk = idx / NP, r = idx - kk * NP;
-      As[idx] = (k0 + kk < nk) ? fa(r, k0 + kk) : mk<TA>(TA(0), TA(0));
+  const int nch = (nk + KC - 1) / KC;
+  cx<TA> ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = threadIdx.x + i * NT;
+      ra[i] = mk<TA>(TA(0), TA(0));
+      rb[i] = mk<TA>(TA(0), TA(0));
+      if (idx < CH) {
+        const int kk = idx / NP, r = idx - kk * NP;
+        if (k0 + kk < nk) ra[i] = fa(r, k0 + kk);
+        const int c = idx / KC, kb = idx - c * KC;
+        if (k0 + kb < nk) rb[i] = fb(k0 + kb, c);
+      }
     }
-    for (int idx = threadIdx.x; idx < KC * NP; idx += NT) {
-      const int c = idx / KC, kk = idx - c * KC;
-      Bs[kk * NP + c] = (k0 + kk < nk) ? fb(k0 + kk, c) : mk<TA>(TA(0), TA(0));
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = threadIdx.x + i * NT;
+      if (idx < CH) {
+        As[buf * CH + idx] = ra[i];
+        const int c = idx / KC, kb = idx - c * KC;
+        Bs[buf * CH + kb * NP + c] = rb[i];
+      }
     }
-    __syncthreads();
+  };
+  if (nch > 0) {
+    fetch(0);
+    put(0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const bool more = ch + 1 < nch;
+    if (more) fetch((ch + 1) * KC);
+    const cx<TA>* Ab = As + (ch & 1) * CH;
+    const cx<TA>* Bb = Bs + (ch & 1) * CH;
 #pragma unroll 1
     for (int kk = 0; kk < KC; ++kk) {
       cx<TA> a[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int r = lane + 64 * s;
-        a[s] = (r < NP) ? As[kk * NP + r] : mk<TA>(TA(0), TA(0));
+        a[s] = (r < NP) ? Ab[kk * NP + r] : mk<TA>(TA(0), TA(0));
       }
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const cx<TA> b = Bs[kk * NP + w * C + j];
+        const cx<TA> b = Bb[kk * NP + w * C + j];
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[s][j] = cfma(a[s], b, acc[s][j]);
+        // bound the broadcast loads in flight (register pressure)
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     }
+    if (more) put((ch + 1) & 1);
     __syncthreads();
   }
 }

@@ -28,7 +28,7 @@
 
 namespace rgf {
 
-constexpr int KC = 8;
+constexpr int KC = 4;
 
 struct SweepArgs {
   int N, L, parity, P;
@@ -56,10 +56,10 @@ struct SweepArgs {
 template <int NW, int S, int C>
 struct SweepSmem {
   static constexpr int NP = NW * C;
-  cx<double> colbuf[2 * NP + 2];   // + 1/pivot x 2; also used as cx<float>
+  cx<double> colbuf[2 * (NP + 1)];  // column and 1/pivot, double-buffered; also cx<float>
   cx<double> wbuf[NW * NP];    // also used as cx<float>[2*NW*NP]
-  cx<double> As[KC * NP];
-  cx<double> Bs[KC * NP];
+  cx<double> As[2 * KC * NP];
+  cx<double> Bs[2 * KC * NP];
   int pivrow[NP];
   int pinv[NP];
   double red[NW * 2];
@@ -246,18 +246,21 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
   const int n1 = half_size(a.N, half_parity(0, a.parity));
   if constexpr (sizeof(TJ) == sizeof(double)) {
     build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
-    __syncthreads();
+    const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));
+    scale_regs(A, f);
     gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.wbuf, sm.pivrow, sm.pinv, &sm.flag);
-    store_unpermuted<double, double, NW, S, C>(A, n, sm.wbuf, sm.pivrow, sm.pinv, Kout,
+    store_unpermuted<double, double, NW, S, C>(A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout,
                                                h == 0 ? G1out : nullptr);
   } else {
     cx<float> AJ[S][C];
     build_M<float, NW, S, C>(AJ, a, q, h, Kprev, sm.wbuf + w * NP);
-    __syncthreads();
+    const float f = tile_scale<float, NW, S, C>(AJ, reinterpret_cast<uint32_t*>(sm.red));
+    scale_regs(AJ, f);
     gj_invert<float, NW, S, C>(AJ, n, reinterpret_cast<cx<float>*>(sm.colbuf),
                                reinterpret_cast<cx<float>*>(sm.wbuf), sm.pivrow, sm.pinv,
                                &sm.flag);
-    store_unpermuted<float, double, NW, S, C>(AJ, n, reinterpret_cast<cx<float>*>(sm.wbuf),
+    store_unpermuted<float, double, NW, S, C>(AJ, n, f,
+                                              reinterpret_cast<cx<float>*>(sm.wbuf),
                                               sm.pivrow, sm.pinv, Kout,
                                               (h == 0 && !REFINE) ? G1out : nullptr);
   }
@@ -316,9 +319,10 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     }
     if (fallback) {
       build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
-      __syncthreads();
+      const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));
+      scale_regs(A, f);
       gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.wbuf, sm.pivrow, sm.pinv, &sm.flag);
-      store_unpermuted<double, double, NW, S, C>(A, n, sm.wbuf, sm.pivrow, sm.pinv, Kout,
+      store_unpermuted<double, double, NW, S, C>(A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout,
                                                  nullptr);
       __syncthreads();
     }
