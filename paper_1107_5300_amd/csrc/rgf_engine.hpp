@@ -74,12 +74,12 @@ __device__ __forceinline__ void zero_regs(cx<T> (&A)[S][C]) {
 // then selects its pivot (a packed 32-bit key reduced across the wave by
 // DPP, no LDS round trip), publishes the column, the pivot row and 1/pivot
 // through double-buffered LDS, and updates its other columns while the
-// other waves do theirs. The raw pivot row of each wave's columns (pivot + 1
-// in column k) is broadcast inside the wave through its LDS scratch.
+// other waves do theirs. Inside each wave the pivot row's entries of the
+// wave's columns (pivot + 1 in column k) go from the pivot lane to all lanes
+// through scalar registers.
 //
-// LDS: colbuf[2][NP + 1] (T: the column, then 1/pivot), wbuf[NW][NP] (T;
-// the first C entries per wave here), pivrow[NP], pinv[NP] (int), flag (int;
-// set to 1 on an exact zero pivot).
+// LDS: colbuf[2][NP + 1] (T: the column, then 1/pivot), pivrow[NP],
+// pinv[NP] (int), flag (int; set to 1 on an exact zero pivot).
 // ----------------------------------------------------------------------------
 // Wave-wide maximum of a 32-bit key by DPP (no LDS traffic); every lane
 // gets the result.
@@ -135,23 +135,6 @@ __device__ __forceinline__ void gj_update_rest(cx<T> (&A)[S][C], const cx<T> (&m
   }
 }
 
-// wbuf[j] = A[ps][j] for the C register columns (ps uniform). The empty
-// asm statement, distinct per slot, keeps the optimiser from merging the
-// branches into one store of a dynamically indexed register (which would
-// move the whole tile to scratch memory).
-template <typename T, int S, int C, int SS>
-__device__ __forceinline__ void gj_write_row(const cx<T> (&A)[S][C], int ps, cx<T>* wbuf) {
-  if constexpr (SS < S) {
-    if (ps == SS) {
-#pragma unroll
-      for (int j = 0; j < C; ++j) wbuf[j] = A[SS][j];
-      asm volatile("; gj row slot %0" ::"n"(SS));
-    } else {
-      gj_write_row<T, S, C, SS + 1>(A, ps, wbuf);
-    }
-  }
-}
-
 // Pivot selection for column kc, held in register column J of the calling
 // (owner) wave: publishes the column, the pivot row and 1/pivot.
 template <typename T, int NW, int S, int C, int J>
@@ -178,10 +161,65 @@ __device__ __forceinline__ void gj_select_pivot(const cx<T> (&A)[S][C], int kc, 
   }
 }
 
-// Elimination step k = kb*C + J (J compile-time).
+// Wave broadcast of lane l's value through a scalar register (l uniform).
+__device__ __forceinline__ double lane_bcast(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_bcast(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// v[g] = A[ps][J0 + g] of lane pl, for g < G except column SKIP (ps and pl
+// uniform). One branch per register slot keeps the register indices
+// constant; the empty asm statement, distinct per slot, keeps the optimiser
+// from merging the branches into a dynamically indexed (scratch) access.
+template <typename T, int S, int C, int J0, int G, int SKIP, int SS>
+__device__ __forceinline__ void gj_row_chunk(const cx<T> (&A)[S][C], int ps, int pl,
+                                             cx<T> (&v)[G]) {
+  if constexpr (SS < S) {
+    if (ps == SS) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (J0 + g != SKIP) v[g] = mk<T>(lane_bcast(A[SS][J0 + g].re, pl),
+                                         lane_bcast(A[SS][J0 + g].im, pl));
+      asm volatile("; gj row chunk slot %0" ::"n"(SS));
+    } else {
+      gj_row_chunk<T, S, C, J0, G, SKIP, SS + 1>(A, ps, pl, v);
+    }
+  }
+}
+
+// Update of the register columns J0.. except SKIP, in chunks of up to 5
+// columns (broadcast the chunk's pivot-row entries, then update it); column
+// J (the pivot column k, owner wave only) takes pivot + 1.
+template <typename T, int S, int C, int J, int SKIP, int J0>
+__device__ __forceinline__ void gj_update_chunks(cx<T> (&A)[S][C], const cx<T> (&m)[S], int ps,
+                                                 int pl, bool own) {
+  if constexpr (J0 < C) {
+    constexpr int G = (C - J0 < 5) ? C - J0 : 5;
+    cx<T> v[G];
+    gj_row_chunk<T, S, C, J0, G, SKIP, 0>(A, ps, pl, v);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (J0 + g == SKIP) continue;
+      cx<T> x = v[g];
+      if (J0 + g == J && own) x.re += T(1);
+#pragma unroll
+      for (int s = 0; s < S; ++s) A[s][J0 + g] = cfms(m[s], x, A[s][J0 + g]);
+    }
+    gj_update_chunks<T, S, C, J, SKIP, J0 + G>(A, m, ps, pl, own);
+  }
+}
+
+// Elimination step k = kb*C + J (J compile-time). The pivot row's entries
+// of this wave's columns go from the pivot lane to the whole wave through
+// scalar registers (readlane), with no LDS traffic.
 template <typename T, int NW, int S, int C, int J>
 __device__ __forceinline__ void gj_step(cx<T> (&A)[S][C], int kb, int n, uint32_t& used,
-                                        cx<T>* colbuf, cx<T>* wbuf, int* pivrow, int* flag) {
+                                        cx<T>* colbuf, int* pivrow, int* flag) {
   constexpr int NP = NW * C;
   constexpr int JN = (J + 1) % C;  // register column of k + 1
   const int lane = lane_id(), w = wave_id();
@@ -199,7 +237,7 @@ __device__ __forceinline__ void gj_step(cx<T> (&A)[S][C], int kb, int n, uint32_
     a[s] = (r < NP) ? cb[r] : mk<T>(T(0), T(0));
   }
   __builtin_amdgcn_sched_barrier(0);
-  const int pk = min(max(pkr, 0), NP - 1);
+  const int pk = __builtin_amdgcn_readfirstlane(min(max(pkr, 0), NP - 1));
   const int pl = pk & 63, ps = pk >> 6;
   cx<T> m[S];
 #pragma unroll
@@ -207,52 +245,38 @@ __device__ __forceinline__ void gj_step(cx<T> (&A)[S][C], int kb, int n, uint32_
     const int r = lane + 64 * s;
     m[s] = (r == pk) ? mk<T>(T(1) - ipiv.re, -ipiv.im) : cmul(a[s], ipiv);
   }
-  // raw pivot row of this wave's columns, with pivot + 1 in column k,
-  // written by the pivot lane (slot ps is wave-uniform: one branch per slot
-  // keeps the register indices constant)
-  if (lane == pl) {
-    gj_write_row<T, S, C, 0>(A, ps, wbuf);
-    if (w == kb) {
-      const cx<T> pv = pick_slot<T, S, C, J>(A, ps);
-      wbuf[J] = mk<T>(pv.re + T(1), pv.im);
-    }
-    used |= 1u << ps;
+  if (lane == pl) used |= 1u << ps;
+  const bool own = (w == kb);
+  {
+    cx<T> v1[1];
+    gj_row_chunk<T, S, C, JN, 1, -1, 0>(A, ps, pl, v1);
+    gj_update_column<T, S, C, JN>(A, m, v1[0]);
   }
-  wave_sync_lds();
-  const cx<T>* prow = wbuf;
-  cx<T> v[C];
-#pragma unroll
-  for (int j = 0; j < C; ++j) v[j] = prow[j];
-  __builtin_amdgcn_sched_barrier(0);
-  gj_update_column<T, S, C, JN>(A, m, v[JN]);
   if (w == kbn && k + 1 < n)
     gj_select_pivot<T, NW, S, C, JN>(A, k + 1, n, used, colbuf, pivrow, flag);
-  gj_update_rest<T, S, C, 0, JN>(A, m, v);
+  gj_update_chunks<T, S, C, J, JN, 0>(A, m, ps, pl, own);
 }
 
 template <typename T, int NW, int S, int C, int J>
 __device__ __forceinline__ void gj_block(cx<T> (&A)[S][C], int kb, int n, uint32_t& used,
-                                         cx<T>* colbuf, cx<T>* wbuf, int* pivrow, int* flag) {
+                                         cx<T>* colbuf, int* pivrow, int* flag) {
   if constexpr (J < C) {
     if (kb * C + J >= n) return;
-    gj_step<T, NW, S, C, J>(A, kb, n, used, colbuf, wbuf, pivrow, flag);
-    gj_block<T, NW, S, C, J + 1>(A, kb, n, used, colbuf, wbuf, pivrow, flag);
+    gj_step<T, NW, S, C, J>(A, kb, n, used, colbuf, pivrow, flag);
+    gj_block<T, NW, S, C, J + 1>(A, kb, n, used, colbuf, pivrow, flag);
   }
 }
 
 template <typename T, int NW, int S, int C>
-__device__ __forceinline__ void gj_invert(cx<T> (&A)[S][C], int n, cx<T>* colbuf,
-                                          cx<T>* wbuf_all, int* pivrow, int* pinv,
-                                          int* flag) {
-  constexpr int NP = NW * C;
+__device__ __forceinline__ void gj_invert(cx<T> (&A)[S][C], int n, cx<T>* colbuf, int* pivrow,
+                                          int* pinv, int* flag) {
   constexpr int NT = NW * 64;
   const int w = wave_id();
-  cx<T>* wbuf = wbuf_all + w * NP;
   uint32_t used = 0;
   if (n > 0 && w == 0) gj_select_pivot<T, NW, S, C, 0>(A, 0, n, used, colbuf, pivrow, flag);
   for (int kb = 0; kb < NW; ++kb) {
     if (kb * C >= n) break;
-    gj_block<T, NW, S, C, 0>(A, kb, n, used, colbuf, wbuf, pivrow, flag);
+    gj_block<T, NW, S, C, 0>(A, kb, n, used, colbuf, pivrow, flag);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += NT) pinv[pivrow[i]] = i;

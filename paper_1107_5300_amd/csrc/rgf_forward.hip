@@ -17,8 +17,13 @@ namespace rgf {
 
 namespace {
 
+// Register budget: an 8-wave workgroup holds two waves per SIMD (one
+// workgroup per compute unit); narrower tilings ask for three waves per SIMD
+// (two with the refinement's extra tiles) so that several workgroups share a
+// compute unit and hide each other's barrier and memory latency.
 template <typename TJ, bool REFINE, int NW, int S, int C>
-__global__ __launch_bounds__(NW * 64) void rgf_fwd_kernel(SweepArgs a) {
+__global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_fwd_kernel(
+    SweepArgs a) {
   constexpr int NP = NW * C;
   __shared__ SweepSmem<NW, S, C> sm;
   cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * NP * NP;

@@ -25,6 +25,7 @@
 
 #include "rgf_engine.hpp"
 #include "rgf_internal.hpp"
+#include "rgf_mfma.hpp"
 
 namespace rgf {
 
@@ -248,7 +249,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
     const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));
     scale_regs(A, f);
-    gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.wbuf, sm.pivrow, sm.pinv, &sm.flag);
+    gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.pivrow, sm.pinv, &sm.flag);
     store_unpermuted<double, double, NW, S, C>(A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout,
                                                h == 0 ? G1out : nullptr);
   } else {
@@ -256,9 +257,8 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     build_M<float, NW, S, C>(AJ, a, q, h, Kprev, sm.wbuf + w * NP);
     const float f = tile_scale<float, NW, S, C>(AJ, reinterpret_cast<uint32_t*>(sm.red));
     scale_regs(AJ, f);
-    gj_invert<float, NW, S, C>(AJ, n, reinterpret_cast<cx<float>*>(sm.colbuf),
-                               reinterpret_cast<cx<float>*>(sm.wbuf), sm.pivrow, sm.pinv,
-                               &sm.flag);
+    gj_invert<float, NW, S, C>(AJ, n, reinterpret_cast<cx<float>*>(sm.colbuf), sm.pivrow,
+                               sm.pinv, &sm.flag);
     store_unpermuted<float, double, NW, S, C>(AJ, n, f,
                                               reinterpret_cast<cx<float>*>(sm.wbuf),
                                               sm.pivrow, sm.pinv, Kout,
@@ -321,7 +321,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
       build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
       const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));
       scale_regs(A, f);
-      gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.wbuf, sm.pivrow, sm.pinv, &sm.flag);
+      gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.pivrow, sm.pinv, &sm.flag);
       store_unpermuted<double, double, NW, S, C>(A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout,
                                                  nullptr);
       __syncthreads();
@@ -332,29 +332,26 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     }
   }
   if (h > 0) {
+    // G1_h = (G1_{h-1} C_{h-1}) g_h on the matrix cores; g_h is complex
+    // symmetric, so it is read transposed (rows contiguous)
     const double t = a.t;
     const cx<double>* G1r = opaque_uniform(G1in);
-    auto fb = [&](int k, int c) -> cx<double> {
-      return (c < n) ? ldg(Kout + (size_t)c * NP + k) : mk(0.0, 0.0);
-    };
     if (!(h & 1)) {
       auto fa = [&](int r, int k) -> cx<double> {
-        return (r < n1) ? cscale(ldg(G1r + (size_t)k * NP + r), t) : mk(0.0, 0.0);
+        return cscale(ldg(G1r + (size_t)k * NP + r), t);
       };
-      gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
+      gemm_mfma<NW, NP>(n1, n, n, fa, Kout, G1out);
     } else {
       const int nL = half_size(a.N, e ^ 1);
       auto fa = [&](int r, int k) -> cx<double> {
-        if (r >= n1) return mk(0.0, 0.0);
         const int k0 = nb_lo(k, e), k1 = nb_hi(k, e);
         cx<double> acc = mk(0.0, 0.0);
         if (k0 >= 0) acc = ldg(G1r + (size_t)k0 * NP + r);
         if (k1 < nL) acc = cadd(acc, ldg(G1r + (size_t)k1 * NP + r));
         return cscale(acc, t);
       };
-      gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
+      gemm_mfma<NW, NP>(n1, n, n, fa, Kout, G1out);
     }
-    store_regs<double, double, NW, S, C>(A, n1, n, G1out);
     __syncthreads();
   }
 }
