@@ -116,6 +116,36 @@ def gpu_run(Es, eps, precision, steps, warmup, tune=True):
     return wall, ev_ms, T.cpu().numpy()[0], st.cpu().numpy()[0], tile
 
 
+def csrc_fingerprint():
+    """sha256 prefix over the HIP sources (the same rule the traffic summary
+    under profiles/ records), so a traffic figure is only reported for the
+    kernel it was measured on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1107_5300_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name):
+    """HBM-side bytes per launch from the committed counter summary, or None
+    when it was taken on another kernel or on other sources."""
+    path = os.path.join(ROOT, "profiles", "rgf_fwd_kernel_disorder_n240_traffic.md")
+    try:
+        with open(path) as fh:
+            line = [ln for ln in fh if ln.startswith("machine-readable: ")][-1]
+        rec = json.loads(line[len("machine-readable: "):])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel") != kernel_name or rec.get("csrc_fingerprint") != csrc_fingerprint():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def copy_calibration(nbytes=1 << 28):
     """A plain device copy of known size, so that a counter run (FETCH_SIZE,
     WRITE_SIZE) can be scaled by what the counters read for it."""
@@ -184,6 +214,10 @@ def main():
     ev_mean_s = float(np.mean(r["ev_ms"])) / 1e3
     flops_call = flops_per_slice_step(N) * steps_per_call
     achieved = flops_call / ev_mean_s / 1e12
+    kname = "rgf_fwd_kernel<%s, %s, %d, %d, %d>" % (
+        "double" if prec == "fp64" else "float", "true" if prec == "mixed" else "false",
+        *(r["tile"][:3] if r["tile"] else (0, 0, 0)))
+    traffic = measured_traffic(kname)
     line = {
         "metric": METRIC,
         "value": value,
@@ -209,9 +243,10 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
-            "kernel": "rgf_fwd_kernel (tile NW,S,C,slots/CU = %s; lead kernels < 0.1 %%)"
-                      % (r["tile"],),
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM side, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": kname,
+            "tile": r["tile"],
             "flops_per_slice_step": flops_per_slice_step(N),
             "dense_equiv_tflops": dense_equiv_flops(N) * steps_per_call / ev_mean_s / 1e12,
             "event_ms_mean": ev_mean_s * 1e3,
