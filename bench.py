@@ -30,6 +30,7 @@ N, L, N_REAL, WDIS = 240, 2000, 1, 0.5
 METRIC = "RGF slice-steps/s at N=240, mixed vs FP64 at |ΔT|≤1e-6; MFMA % of peak"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 (vector and matrix), 256 CU x 2.4 GHz
 ACC_TOL = 1e-6
+GRAD_TOL = 1e-5  # max |dT/deps - oracle| / max |oracle|, adjoint row
 
 
 def flops_per_slice_step(N):
@@ -67,8 +68,12 @@ def cpu_baseline(Es, eps, max_workers=16):
     os.environ["MKL_NUM_THREADS"] = "1"
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    with ctx.Pool(nw) as pool:
+    pool = ctx.Pool(nw)
+    try:
         res = pool.map(_oracle_job, [(int(j), Es[j], eps) for j in idx])
+    finally:
+        pool.close()   # let the workers exit on their own (no SIGTERM)
+        pool.join()
     wall = time.perf_counter() - t0
     rate = len(idx) * L / wall
     return {
@@ -159,6 +164,223 @@ def copy_calibration(nbytes=1 << 28):
     return nbytes
 
 
+# ----------------------------------------------------------------------------- other rows
+#
+# `--row adjoint` and `--row batched` measure the gradient sweep (workload
+# adjoint_n120) and the mixed-width batched launch (workload batched_mixed at
+# 256 of its 4096 energies) with the same conventions: HIP events on the
+# launch stream, the oracle on a bounded sample for accuracy and the CPU
+# rate, one JSON line.
+
+def _say(*a):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def _pool_map(fn, jobs, max_workers=16):
+    import multiprocessing as mp
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    os.environ.update({k: "1" for k in keys})
+    try:
+        nw = max(1, min(max_workers, len(jobs), len(os.sched_getaffinity(0))))
+        t0 = time.perf_counter()
+        pool = mp.get_context("spawn").Pool(nw)
+        try:
+            res = pool.map(fn, jobs)
+        finally:
+            pool.close()   # let the workers exit on their own (no SIGTERM)
+            pool.join()
+        return res, time.perf_counter() - t0, nw
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def _oracle_grad_job(args):
+    n, l, E, eps = args
+    import oracle as O
+    return O.transmission_grad(n, l, W.T_HOP, W.ETA, float(E), eps, 0)
+
+
+def _oracle_T_job(args):
+    n, l, E, eps = args
+    import oracle as O
+    return O.transmission(n, l, W.T_HOP, W.ETA, float(E), eps, 0)
+
+
+def _events(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, [a.elapsed_time(b) for a, b in evs]
+
+
+def row_adjoint(args):
+    """Gradient sweep, workload adjoint_n120: rgf_grad over 128 energies with
+    weights 1/n_E (the gradient of the mean conductance)."""
+    import torch
+
+    import paper_1107_5300_amd as P
+    n, l = 120, 500
+    Es = W.energies("adjoint_n120")
+    eps = W.disorder(l, n, 0.3, r=0)
+    sample = [0, 37, 64, 101]
+    cpu_jobs = [(n, l, Es[j], eps) for j in np.linspace(0, len(Es) - 1, 16).round().astype(int)]
+    cpu = None
+    if not args.no_cpu:
+        _, wall_c, nw = _pool_map(_oracle_grad_job, cpu_jobs)
+        cpu = {"value": len(cpu_jobs) * l / wall_c, "unit": "slice-steps/s (forward+gradient)",
+               "cores": nw, "kind": "oracle",
+               "sample": f"{len(cpu_jobs)} of {len(Es)} energies at full length, oracle forward + "
+                         f"backward sweep, one energy per process; {wall_c:.1f} s wall"}
+    want = None
+    if not args.no_cpu:
+        want, _, _ = _pool_map(_oracle_grad_job, [(n, l, Es[j], eps) for j in sample])
+        _say("adjoint: oracle sample done")
+    dev = torch.device("cuda:0")
+    rib = P.Ribbon(n, l, 0, W.T_HOP, W.ETA)
+    E = torch.tensor(Es, device=dev)
+    ep = torch.tensor(eps[None], device=dev)
+    w = torch.full((1, len(Es)), 1.0 / len(Es), dtype=torch.float64, device=dev)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        tile = P.autotune(rib, prec)
+        ws = P.Workspace()
+        wall, ev = _events(torch, lambda: P.grad(rib, E, ep, w, precision=prec, workspace=ws),
+                           args.steps, args.warmup)
+        # accuracy: one-hot weights on the sampled energies, against the oracle
+        derr, terr = (0.0, 0.0) if want is not None else (None, None)
+        for j, (Tw, gw) in zip(sample, want or []):
+            oh = torch.zeros_like(w)
+            oh[0, j] = 1.0
+            T, g = P.grad(rib, E, ep, oh, precision=prec, workspace=ws)
+            g = g.cpu().numpy()[0]
+            derr = max(derr, float(np.abs(g - gw).max() / max(np.abs(gw).max(), 1e-30)))
+            terr = max(terr, float(abs(T.cpu().numpy()[0, j] - Tw)))
+        out[prec] = dict(wall=wall, ev=ev, derr=derr, terr=terr, tile=tile)
+        _say(f"adjoint {prec}: {wall / args.steps:.3f} s per step")
+    ok = [p for p in out if out[p]["terr"] is not None and out[p]["terr"] <= ACC_TOL
+          and out[p]["derr"] <= GRAD_TOL] or list(out)
+    prec = min(ok, key=lambda p: out[p]["wall"])
+    r = out[prec]
+    steps = len(Es) * l
+    ev_s = float(np.mean(r["ev"])) / 1e3
+    fl = 3 * flops_per_slice_step(n)
+    line = {
+        "metric": "adjoint RGF slice-steps/s (forward + gradient) at N=120",
+        "value": steps * args.steps / r["wall"], "unit": "slice-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall"] / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed": "f32+f64"}[prec], "data": "synthetic",
+        "config": {"workload": "adjoint_n120", "N": n, "L": l, "n_energies": len(Es),
+                   "n_real": 1, "disorder": f"U[-0.3|t|,0.3|t|] seed {W.SEED_BASE}",
+                   "precision": prec, "slice_steps_per_step": steps},
+        "roofline": {"bound": "alu", "achieved": fl * steps / ev_s / 1e12,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fl * steps / ev_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "rgf_grad_kernel", "tile": r["tile"],
+                     "flops_per_slice_step": fl, "event_ms_mean": ev_s * 1e3},
+        "cpu_baseline": cpu,
+        "accuracy": {"sampled_energies": sample, "max_abs_dT_vs_oracle": r["terr"],
+                     "max_rel_grad_err_vs_oracle": r["derr"], "bar_T": ACC_TOL,
+                     "bar_grad_rel": GRAD_TOL},
+        "rates": {p: {"slice_steps_per_s": steps * args.steps / out[p]["wall"],
+                      "max_abs_dT_vs_oracle": out[p]["terr"],
+                      "max_rel_grad_err_vs_oracle": out[p]["derr"], "tile": out[p]["tile"]}
+                  for p in out},
+    }
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
+          flush=True)
+
+
+def row_batched(args):
+    """Mixed-width batched launch, workload batched_mixed at every 16th of its
+    4096 energies (256, 32 of them in |E| < 0.05|t|): widths 60, 120, 240,
+    L = 1000, 16 realizations, one rgf_conductance_batched call."""
+    import torch
+
+    import paper_1107_5300_amd as P
+    widths, l, nreal = (60, 120, 240), 1000, 16
+    Es = W.energies("batched_mixed")[::16]
+    epss = [W.disorder_batch(l, n, 0.5, nreal) for n in widths]
+    rng = np.random.default_rng(7)
+    checks = [(d, int(rng.integers(nreal)), int(rng.integers(len(Es)))) for d in range(3)
+              for _ in range(4)]
+    cpu = None
+    if not args.no_cpu:
+        jobs = [(widths[d], l, Es[e], epss[d][r]) for d, r, e in checks]
+        want, wall_c, nw = _pool_map(_oracle_T_job, jobs)
+        _say(f"batched: oracle sample done in {wall_c:.1f} s")
+        steps_c = len(jobs) * l
+        cpu = {"value": steps_c / wall_c, "unit": "slice-steps/s", "cores": nw, "kind": "oracle",
+               "sample": f"{len(jobs)} (width, realization, energy) tuples, 4 per width, at full "
+                         f"length, one per process; {wall_c:.1f} s wall"}
+    else:
+        want = None
+    dev = torch.device("cuda:0")
+    ribs = [P.Ribbon(n, l, 0, W.T_HOP, W.ETA) for n in widths]
+    E = torch.tensor(Es, device=dev)
+    eps_d = [torch.tensor(e, device=dev) for e in epss]
+    out = {}
+    for prec in ("fp64", "mixed"):
+        tiles = [P.autotune(rb, prec) for rb in ribs]
+        ws = P.Workspace()
+        res = {}
+
+        def call():
+            res["T"] = P.conductance_batched(ribs, E, eps_d, precision=prec, workspace=ws)
+        wall, ev = _events(torch, call, args.steps, args.warmup)
+        Ts = [t.cpu().numpy() for t in res["T"]]
+        err = None if want is None else max(abs(Ts[d][r, e] - v) for (d, r, e), v in
+                                             zip(checks, want))
+        out[prec] = dict(wall=wall, ev=ev, err=err, tiles=tiles, T=Ts)
+        _say(f"batched {prec}: {wall / args.steps:.3f} s per step")
+    dmix = max(float(np.abs(a - b).max()) for a, b in zip(out["mixed"]["T"], out["fp64"]["T"]))
+    out["mixed"]["vs64"], out["fp64"]["vs64"] = dmix, 0.0
+    ok = [p for p in out if (out[p]["err"] if out[p]["err"] is not None else out[p]["vs64"])
+          <= ACC_TOL] or list(out)
+    prec = min(ok, key=lambda p: out[p]["wall"])
+    r = out[prec]
+    steps = len(widths) * nreal * len(Es) * l
+    ev_s = float(np.mean(r["ev"])) / 1e3
+    flops = sum(flops_per_slice_step(n) * nreal * len(Es) * l for n in widths)
+    line = {
+        "metric": "batched RGF slice-steps/s, widths {60,120,240} in one call",
+        "value": steps * args.steps / r["wall"], "unit": "slice-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall"] / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed": "f32+f64"}[prec], "data": "synthetic",
+        "config": {"workload": "batched_mixed (256 of 4096 energies)", "N": list(widths), "L": l,
+                   "n_energies": len(Es), "n_real": nreal, "precision": prec,
+                   "slice_steps_per_step": steps},
+        "roofline": {"bound": "alu", "achieved": flops / ev_s / 1e12, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / ev_s / 1e12 / PEAK_FP64_TFLOPS,
+                     "traffic": None, "kernel": "rgf_fwd_kernel (one launch per width)",
+                     "tiles": r["tiles"], "event_ms_mean": ev_s * 1e3},
+        "cpu_baseline": cpu,
+        "accuracy": {"checked_tuples": checks, "max_abs_dT_vs_oracle": r["err"],
+                     "max_abs_dT_mixed_vs_fp64_all": dmix, "bar": ACC_TOL},
+        "rates": {p: {"slice_steps_per_s": steps * args.steps / out[p]["wall"],
+                      "max_abs_dT_vs_oracle": out[p]["err"], "tiles": out[p]["tiles"]}
+                  for p in out},
+    }
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,16 +389,24 @@ def main():
     ap.add_argument("--precision", default="auto", choices=["fp64", "mixed", "fp32", "auto"],
                     help="auto: time fp64 and mixed, report the faster one that meets "
                          "|dT| <= 1e-6 against the oracle sample")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle legs (baseline and accuracy samples)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--row", default="main", choices=["main", "adjoint", "batched"],
+                    help="main: the N=240 sweep (the metric); adjoint: gradient sweep of the "
+                         "N=120 workload; batched: the mixed-width batched launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(tuples would shard across GPUs with one gather of T; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.row == "adjoint":
+        return row_adjoint(args)
+    if args.row == "batched":
+        return row_batched(args)
 
     Es = W.energies(WORKLOAD)
     eps = W.disorder(L, N, WDIS, r=0)
@@ -184,6 +414,7 @@ def main():
     cpu, oracle_T = (None, {})
     if not args.no_cpu:
         cpu, oracle_T = cpu_baseline(Es, eps)
+        _say(f"cpu baseline: {cpu['value']:.0f} slice-steps/s")
 
     steps_per_call = N_REAL * len(Es) * L
     modes = ["fp64", "mixed"] if args.precision == "auto" else [args.precision]
@@ -193,6 +424,7 @@ def main():
                                            tune=not args.no_tune)
         dT = max((abs(T[j] - v) for j, v in oracle_T.items()), default=None)
         results[prec] = dict(wall=wall, ev_ms=ev_ms, T=T, st=st, dT=dT, tile=tile)
+        _say(f"{prec}: {wall / args.steps * 1e3:.1f} ms per step")
     if args.calibrate_copy:
         copy_calibration()
     if "fp64" in results and "mixed" in results:

@@ -44,6 +44,55 @@ def _stale(obj, src):
     return any(os.path.getmtime(d) > t for d in deps)
 
 
+def _parse_remarks(text):
+    """Per-kernel resource usage from -Rpass-analysis=kernel-resource-usage."""
+    import re
+    rec, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+            rec[cur] = {}
+            continue
+        m = re.search(r"remark:\s+([^:]+): (\S+) \[", line)
+        if m and cur:
+            rec[cur][m.group(1).strip()] = m.group(2)
+    return rec
+
+
+def _demangle(names):
+    try:
+        r = subprocess.run(["c++filt"], input="\n".join(names).encode(), stdout=subprocess.PIPE,
+                           stderr=subprocess.DEVNULL, timeout=60)
+        out = r.stdout.decode().splitlines()
+        if len(out) == len(names):
+            return out
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return list(names)
+
+
+def write_resource_report(objdir):
+    """_build/kernel_resources.txt: VGPRs, scratch bytes per lane, spills and
+    occupancy of every kernel, from the compiler's resource remarks."""
+    rec = {}
+    for src in SOURCES:
+        path = os.path.join(objdir, os.path.splitext(src)[0] + ".remarks")
+        if os.path.exists(path):
+            with open(path) as fh:
+                rec.update(_parse_remarks(fh.read()))
+    names = sorted(rec)
+    lines = ["kernel\tVGPRs\tAGPRs\tscratch_bytes_per_lane\tVGPR_spill\tSGPR_spill\twaves_per_SIMD"]
+    for mangled, pretty in zip(names, _demangle(names)):
+        r = rec[mangled]
+        pretty = pretty.replace("rgf::(anonymous namespace)::", "").replace("(rgf::SweepArgs)", "")
+        lines.append("\t".join([pretty, r.get("VGPRs", "?"), r.get("AGPRs", "?"),
+                                r.get("ScratchSize [bytes/lane]", "?"), r.get("VGPRs Spill", "?"),
+                                r.get("SGPRs Spill", "?"), r.get("Occupancy [waves/SIMD]", "?")]))
+    with open(os.path.join(objdir, "kernel_resources.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def build(verbose=False, jobs=None, incremental=False):
     """Compile every source to an object in parallel, then link librgf.so.
     incremental=True skips objects that are newer than their inputs (for
@@ -58,9 +107,11 @@ def build(verbose=False, jobs=None, incremental=False):
         objs.append(obj)
         if incremental and not _stale(obj, src):
             continue
-        cmd = [cc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        remarks = ["-Rpass-analysis=kernel-resource-usage"]
+        cmd = [cc] + HIP_FLAGS + remarks + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [cc, "-x", "hip"] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [cc, "-x", "hip"] + HIP_FLAGS + remarks + ["-c", os.path.join(CSRC, src),
+                                                            "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -68,7 +119,10 @@ def build(verbose=False, jobs=None, incremental=False):
     for src, pr in procs:
         out, _ = pr.communicate()
         text = out.decode(errors="replace")
-        lines = [ln for ln in text.splitlines() if "packed-fp32-ops" not in ln]
+        with open(os.path.join(objdir, os.path.splitext(src)[0] + ".remarks"), "w") as fh:
+            fh.write(text)
+        lines = [ln for ln in text.splitlines()
+                 if "packed-fp32-ops" not in ln and "kernel-resource-usage" not in ln]
         if pr.returncode != 0:
             failed.append((src, "\n".join(lines)))
         elif verbose and lines:
@@ -84,6 +138,7 @@ def build(verbose=False, jobs=None, incremental=False):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))
     os.replace(tmp, LIB)
+    write_resource_report(objdir)
     return LIB
 
 

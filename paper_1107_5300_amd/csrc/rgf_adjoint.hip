@@ -137,7 +137,7 @@ __global__ __launch_bounds__(NW * 64) void rgf_grad_kernel(SweepArgs a) {
         return (c < n1) ? mk(phiL[(size_t)k * NP + c], 0.0) : mk(0.0, 0.0);
       };
       gemm_regs<double, NW, S, C, KC>(A, a.P, fa, fb, sm.As, sm.Bs);
-      store_regs<double, double, NW, S, C>(A, nlast, n1, zbuf);
+      store_regs_rowmajor<double, double, NW, S, C>(A, nlast, n1, zbuf);
       __syncthreads();
     }
 
@@ -154,62 +154,69 @@ __global__ __launch_bounds__(NW * 64) void rgf_grad_kernel(SweepArgs a) {
         cx<double>* Ko = sg + (size_t)j * 2 * MAT;
         half_step<TJ, REFINE, NW, S, C>(a, q, h, Kp, Ko, Gp, Ko + MAT, rbuf, A, sm);
       }
-      // step Z and Q back through the segment
+      // step Z and Q back through the segment; both are kept row-major
+      // (X[r][c] at r*NP + c), so the matrix-core GEMMs read C_h X along rows
+      // and write their results with contiguous columns
       for (int h = h1 - 1; h >= h0; --h) {
-        const cx<double>* gh = sg + (size_t)(h - h0) * 2 * MAT;
+        const cx<double>* gh = opaque_uniform(sg + (size_t)(h - h0) * 2 * MAT);
         const cx<double>* G1h = gh + MAT;
         const int e = half_parity(h, a.parity);
         const int n = half_size(a.N, e);
+        if (threadIdx.x < NP) sm.rowacc[threadIdx.x] = 0.0;
         if (h < H - 1) {
           const int en = half_parity(h + 1, a.parity);
           const int nn = half_size(a.N, en);
           const double t = a.t;
-          // (C_h X)[a][c]: h even (L_i -> R_i): t * (X[a + 1 - eR][c] + X[a - eR][c]);
-          //                h odd  (R_i -> L_{i+1}): t * X[a][c]
-          auto cx_apply = [&](const cx<double>* X, int k, int c) -> cx<double> {
-            if (c >= n1 || k >= n) return mk(0.0, 0.0);
-            if (h & 1) return cscale(ldg(X + (size_t)c * NP + k), t);
+          // (C_h X)[k][c]: h even (L_i -> R_i): t * (X[k + 1 - eR][c] + X[k - eR][c]);
+          //                h odd  (R_i -> L_{i+1}): t * X[k][c]
+          auto capply = [&](const cx<double>* X, int k, int c) -> cx<double> {
+            if (h & 1) return cscale(ldg(X + (size_t)k * NP + c), t);
             const int b0 = k + 1 - en, b1 = k - en;
             cx<double> acc = mk(0.0, 0.0);
-            if (b0 >= 0 && b0 < nn) acc = ldg(X + (size_t)c * NP + b0);
-            if (b1 >= 0 && b1 < nn) acc = cadd(acc, ldg(X + (size_t)c * NP + b1));
+            if (b0 >= 0 && b0 < nn) acc = ldg(X + (size_t)b0 * NP + c);
+            if (b1 >= 0 && b1 < nn) acc = cadd(acc, ldg(X + (size_t)b1 * NP + c));
             return cscale(acc, t);
           };
-          auto fa = [&](int r, int k) -> cx<double> {
-            return (r < n) ? ldg(gh + (size_t)k * NP + r) : mk(0.0, 0.0);
-          };
+          auto fa = [&](int r, int k) -> cx<double> { return ldg(gh + (size_t)k * NP + r); };
+          // Z_h = g_h (C_h Z_{h+1}), in place
           {
-            auto fb = [&](int k, int c) -> cx<double> { return cx_apply(zbuf, k, c); };
-            gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
-            store_regs<double, double, NW, S, C>(A, n, n1, zbuf);
+            auto fb = [&](int k, int c) -> cx<double> { return capply(zbuf, k, c); };
+            auto epi = [&](int r, int c, cx<double> v, bool ok) {
+              if (ok) stg(zbuf + (size_t)r * NP + c, v);
+            };
+            gemm_mfma<NW, NP>(n, n1, n, fa, fb, epi);
           }
+          // Q_h = G1_h^T + g_h (C_h Q_{h+1}), in place, and the row sums
+          // sum_c Re(Z_h[a][c] Q_h[a][c]) (16 columns per row group, then LDS)
           {
-            auto fb = [&](int k, int c) -> cx<double> { return cx_apply(qbuf, k, c); };
-            gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
+            auto fb = [&](int k, int c) -> cx<double> { return capply(qbuf, k, c); };
+            auto epi = [&](int r, int c, cx<double> v, bool ok) {
+              double part = 0.0;
+              if (ok) {
+                v = cadd(v, ldg(G1h + (size_t)r * NP + c));  // G1_h^T[r][c] = G1_h[c][r]
+                const cx<double> z = ldg(zbuf + (size_t)r * NP + c);
+                part = z.re * v.re - z.im * v.im;
+                stg(qbuf + (size_t)r * NP + c, v);
+              }
+              part += __shfl_xor(part, 1);
+              part += __shfl_xor(part, 2);
+              part += __shfl_xor(part, 4);
+              part += __shfl_xor(part, 8);
+              if ((lane_id() & 15) == 0 && r < n) atomicAdd(&sm.rowacc[r], part);
+            };
+            gemm_mfma<NW, NP>(n, n1, n, fa, fb, epi);
           }
         } else {
-          zero_regs(A);
-        }
-        // Q_h = G1_h^T + (g_h C_h Q_{h+1}); rows a < n, columns c < n1
-        if (threadIdx.x < NP) sm.rowacc[threadIdx.x] = 0.0;
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int r = lane + 64 * s;
-          double acc = 0.0;
-#pragma unroll
-          for (int j = 0; j < C; ++j) {
-            const int c = w * C + j;
-            if (r < n && c < n1) {
-              const cx<double> gt = ldg(G1h + (size_t)r * NP + c);
-              A[s][j] = cadd(A[s][j], gt);
-              const cx<double> z = ldg(zbuf + (size_t)c * NP + r);
-              acc += z.re * A[s][j].re - z.im * A[s][j].im;
-            }
+          // last half-slice: Z = Z_last (already in zbuf), Q = G1^T
+          __syncthreads();
+          for (int i = threadIdx.x; i < n * n1; i += NW * 64) {
+            const int r = i / n1, c = i - r * n1;
+            const cx<double> v = ldg(G1h + (size_t)r * NP + c);
+            const cx<double> z = ldg(zbuf + (size_t)r * NP + c);
+            stg(qbuf + (size_t)r * NP + c, v);
+            atomicAdd(&sm.rowacc[r], z.re * v.re - z.im * v.im);
           }
-          if (r < n) atomicAdd(&sm.rowacc[r], acc);
         }
-        store_regs<double, double, NW, S, C>(A, n, n1, qbuf);
         __syncthreads();
         if (threadIdx.x < n) {
           const int i = h >> 1;
@@ -248,7 +255,7 @@ struct GradEntry {
 const GradEntry kGrad[] = {
     RGF_GRAD_ENTRY(1, 1, 8),  RGF_GRAD_ENTRY(1, 1, 16), RGF_GRAD_ENTRY(2, 1, 16),
     RGF_GRAD_ENTRY(4, 1, 12), RGF_GRAD_ENTRY(4, 1, 15), RGF_GRAD_ENTRY(4, 1, 16),
-    RGF_GRAD_ENTRY(8, 2, 12), RGF_GRAD_ENTRY(8, 2, 15), RGF_GRAD_ENTRY(8, 2, 16),
+    RGF_GRAD_ENTRY(8, 1, 8),  RGF_GRAD_ENTRY(8, 2, 12), RGF_GRAD_ENTRY(8, 2, 15), RGF_GRAD_ENTRY(8, 2, 16),
 };
 
 }  // namespace

@@ -387,6 +387,25 @@ __device__ __forceinline__ void store_regs(const cx<T> (&X)[S][C], int nr, int n
   }
 }
 
+// Store registers (natural order) to a row-major buffer, ld = NP: K[r*NP + c]
+// for r < nr, c < nc.
+template <typename T, typename TG, int NW, int S, int C>
+__device__ __forceinline__ void store_regs_rowmajor(const cx<T> (&X)[S][C], int nr, int nc,
+                                                    cx<TG>* K) {
+  const int lane = lane_id(), w = wave_id();
+  K = opaque_uniform(K);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int c = w * C + j;
+    if (c >= nc) break;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = lane + 64 * s;
+      if (r < nr) stg(K + (size_t)r * NW * C + c, mk<TG>((TG)X[s][j].re, (TG)X[s][j].im));
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------
 // acc[r][c] = sum_{k < nk} fa(r, k) * fb(k, c) for the NP x NP register tile.
 // The accessors return zero outside the operand shapes. KC columns of fa and

@@ -71,7 +71,7 @@ struct FwdEntry {
 const FwdEntry kFwd[] = {
     RGF_FWD_ENTRY(1, 1, 8),  RGF_FWD_ENTRY(1, 1, 16), RGF_FWD_ENTRY(2, 1, 16),
     RGF_FWD_ENTRY(4, 1, 12), RGF_FWD_ENTRY(4, 1, 15), RGF_FWD_ENTRY(4, 1, 16),
-    RGF_FWD_ENTRY(8, 2, 12), RGF_FWD_ENTRY(8, 2, 15), RGF_FWD_ENTRY(8, 2, 16),
+    RGF_FWD_ENTRY(8, 1, 8),  RGF_FWD_ENTRY(8, 2, 12), RGF_FWD_ENTRY(8, 2, 15), RGF_FWD_ENTRY(8, 2, 16),
 };
 
 }  // namespace

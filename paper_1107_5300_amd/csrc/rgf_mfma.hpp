@@ -1,5 +1,6 @@
-// rgf_mfma.hpp -- FP64 complex GEMM on the CDNA matrix cores for the update
-// of the running propagator G1_h = (G1_{h-1} C_{h-1}) g_h.
+// rgf_mfma.hpp -- FP64 complex GEMM on the CDNA matrix cores: the update of
+// the running propagator G1_h = (G1_{h-1} C_{h-1}) g_h and the reverse
+// sweep's products g_h (C_h Z_{h+1}), g_h (C_h Q_{h+1}).
 //
 // v_mfma_f64_16x16x4f64 computes D = A B + D for a 16 x 4 block A, a 4 x 16
 // block B and a 16 x 16 block D, one double per lane for A and B and four
@@ -68,25 +69,24 @@ __device__ __forceinline__ void mfma_complex_step(mf64x4 (&accr)[TR][TC], mf64x4
   }
 }
 
-// out[c*NP + r] = sum_{k < nk} fa(r, k) * Bt[k*NP + c]   for r < nr, c < nc.
-// fa(r, k) gives the left operand (called for r < nr, k < nk only); the
-// right operand is read transposed from the column-major buffer Bt, i.e. the
-// product is A * Bt^T (= A * Bt when Bt holds a symmetric matrix; the
-// inverse of the complex-symmetric M_h is symmetric). Both operands are
-// loaded straight from memory one k-step ahead, as 16-byte accesses that
-// are contiguous across the 16 lanes of a row group. The results are stored
-// after a workgroup barrier, so out may alias the memory fa reads.
-template <int NW, int NP, typename FA>
-__device__ __forceinline__ void gemm_mfma(int nr, int nc, int nk, FA fa, const cx<double>* Bt,
-                                          cx<double>* out) {
+// D[r][c] = sum_{k < nk} fa(r, k) * fb(k, c)   for r < nr, c < nc, handed to
+// epi(r, c, D[r][c], valid) after a workgroup barrier (so the epilogue may
+// write memory that fa or fb read). The epilogue runs on every lane of a
+// wave whose block intersects the output, with valid = (r < nr && c < nc),
+// so it may reduce across lanes. fa is called for r < nr, k < nk and fb for
+// k < nk, c < nc only; each is called with 16 consecutive rows (fa) or
+// columns (fb) across the lanes of a row group, so loads that are
+// contiguous in that index coalesce. Operands are loaded one k-step ahead.
+// In the epilogue the 16 lanes l % 16 = 0..15 of a row group hold 16
+// consecutive columns of one row (lane l, element v: row 4 v + l / 16).
+template <int NW, int NP, typename FA, typename FB, typename EPI>
+__device__ __forceinline__ void gemm_mfma(int nr, int nc, int nk, FA fa, FB fb, EPI epi) {
   constexpr int PT = (NP + 15) / 16;
   constexpr int WR = WaveGrid<NW>::WR, WC = WaveGrid<NW>::WC;
   constexpr int TR = (PT + WR - 1) / WR, TC = (PT + WC - 1) / WC;
   const int lane = lane_id(), w = wave_id();
   const int li = lane & 15, lk = lane >> 4;
   const int r0 = (w / WC) * TR * 16, c0 = (w % WC) * TC * 16;
-  Bt = opaque_uniform(Bt);
-  out = opaque_uniform(out);
   mf64x4 accr[TR][TC], acci[TR][TC];
 #pragma unroll
   for (int i = 0; i < TR; ++i)
@@ -105,7 +105,7 @@ __device__ __forceinline__ void gemm_mfma(int nr, int nc, int nk, FA fa, const c
 #pragma unroll
     for (int j = 0; j < TC; ++j) {
       const int c = c0 + j * 16 + li;
-      b[j] = (c < nc && k < nk) ? ldg(Bt + (size_t)k * NP + c) : mk(0.0, 0.0);
+      b[j] = (c < nc && k < nk) ? fb(k, c) : mk(0.0, 0.0);
     }
   };
   if (r0 < nr && c0 < nc) {
@@ -129,7 +129,7 @@ __device__ __forceinline__ void gemm_mfma(int nr, int nc, int nk, FA fa, const c
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = r0 + i * 16 + 4 * v + lk;
-          if (r < nr && c < nc) stg(out + (size_t)c * NP + r, mk(accr[i][j][v], acci[i][j][v]));
+          epi(r, c, mk(accr[i][j][v], acci[i][j][v]), r < nr && c < nc);
         }
       }
   }

@@ -336,11 +336,17 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     // symmetric, so it is read transposed (rows contiguous)
     const double t = a.t;
     const cx<double>* G1r = opaque_uniform(G1in);
+    const cx<double>* Kg = opaque_uniform(Kout);
+    cx<double>* G1w = opaque_uniform(G1out);
+    auto fb = [&](int k, int c) -> cx<double> { return ldg(Kg + (size_t)k * NP + c); };
+    auto epi = [&](int r, int c, cx<double> v, bool ok) {
+      if (ok) stg(G1w + (size_t)c * NP + r, v);
+    };
     if (!(h & 1)) {
       auto fa = [&](int r, int k) -> cx<double> {
         return cscale(ldg(G1r + (size_t)k * NP + r), t);
       };
-      gemm_mfma<NW, NP>(n1, n, n, fa, Kout, G1out);
+      gemm_mfma<NW, NP>(n1, n, n, fa, fb, epi);
     } else {
       const int nL = half_size(a.N, e ^ 1);
       auto fa = [&](int r, int k) -> cx<double> {
@@ -350,7 +356,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
         if (k1 < nL) acc = cadd(acc, ldg(G1r + (size_t)k1 * NP + r));
         return cscale(acc, t);
       };
-      gemm_mfma<NW, NP>(n1, n, n, fa, Kout, G1out);
+      gemm_mfma<NW, NP>(n1, n, n, fa, fb, epi);
     }
     __syncthreads();
   }

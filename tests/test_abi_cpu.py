@@ -104,3 +104,19 @@ def test_lead_sizes_query():
         assert lib.rgf_lead_self_energy(ctypes.byref(d), None, 0, None, None, None,
                                         ctypes.byref(a), ctypes.byref(b), None, 0, None) == 0
         assert (a.value, b.value) == (nl, nr), (N, Lc, par)
+
+
+def test_forward_kernels_use_no_scratch():
+    """The forward sweep kernels keep their register tiles in registers: a
+    kernel that needs scratch memory (a spilled or dynamically indexed tile)
+    is several times slower. Reads the resource report the build writes."""
+    from paper_1107_5300_amd import _lib as L
+    path = os.path.join(os.path.dirname(L.LIB_PATH), "_build", "kernel_resources.txt")
+    if not os.path.exists(path):
+        pytest.skip("no resource report (library not built in this tree)")
+    with open(path) as fh:
+        rows = [ln.rstrip("\n").split("\t") for ln in fh][1:]
+    fwd = [r for r in rows if "rgf_fwd_kernel<" in r[0] and "true" not in r[0]]
+    assert len(fwd) >= 20, "report lists too few forward kernels"
+    bad = [(r[0], r[3], r[4]) for r in fwd if r[3] != "0" or r[4] != "0"]
+    assert not bad, f"forward kernels with scratch / VGPR spills: {bad}"
