@@ -91,6 +91,19 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   q.want_grad = want_grad != 0;
   if (!pick_tile(q.nmax, precision, &q.tile))
     return fail(RGF_ERR_UNSUPPORTED, "width_n = %d exceeds the register tiling", q.N);
+  if (q.want_grad && q.ntuples <= device_cu_count()) {
+    // Fewer tuples than compute units: each workgroup runs one tuple at a
+    // time and the sweep is latency-bound, so prefer the tiling with the
+    // most waves per tuple among those that pad n by at most a quarter.
+    TileCfg best = q.tile;
+    for (int i = 0; i < tile_count(); ++i) {
+      const TileCfg c = tile_at(i);
+      const int np = c.NP();
+      if (np < q.nmax || 64 * c.S < np || 4 * np > 5 * q.nmax + 32) continue;
+      if (c.NW > best.NW || (c.NW == best.NW && np < best.NP())) best = c;
+    }
+    q.tile = best;
+  }
   const int NP = q.tile.NP();
   {
     int tid = 0, per_cu = 0;
@@ -148,6 +161,15 @@ bool tuned_choice(int n, int precision, int* tile_id, int* per_cu) {
 void set_tuned_choice(int n, int precision, int tile_id, int per_cu) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[{n, precision}] = {tile_id, per_cu};
+}
+
+int device_cu_count() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    return prop.multiProcessorCount;
+  (void)hipGetLastError();
+  return 256;
 }
 
 int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad, int per_cu) {

@@ -94,6 +94,17 @@ __device__ __forceinline__ cx<T> crcp(cx<T> b) {
   }
 }
 
+// 1/b = conj(b) / |b|^2 with one division, for arguments of moderate
+// magnitude (the pivots of a tile scaled to entries below 1): |b|^2 cannot
+// overflow there, and it underflows only for pivots so small that the
+// inversion has no accurate digits left (the result is then infinite and
+// the tuple reports a non-finite conductance).
+template <typename T>
+__device__ __forceinline__ cx<T> crcp_scaled(cx<T> b) {
+  const T inv = T(1) / fma(b.re, b.re, b.im * b.im);
+  return mk<T>(b.re * inv, -b.im * inv);
+}
+
 // |re| + |im|: the pivot magnitude of LAPACK-style complex pivoting.
 template <typename T>
 __device__ __forceinline__ T cabs1(cx<T> a) {

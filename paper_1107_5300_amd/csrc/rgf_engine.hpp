@@ -156,7 +156,7 @@ __device__ __forceinline__ void gj_select_pivot(const cx<T> (&A)[S][C], int kc, 
   if (lane == (pk & 63)) {
     const cx<T> pv = pick_slot<T, S, C, J>(A, pk >> 6);
     pivrow[kc] = pk;
-    cb[NP] = crcp(pv);
+    cb[NP] = crcp_scaled(pv);
     if (!(cabs1(pv) > T(0))) *flag = 1;
   }
 }

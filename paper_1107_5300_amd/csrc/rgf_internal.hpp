@@ -25,6 +25,7 @@ bool pick_tile(int n, int precision, TileCfg* out);
 
 // All tilings (in table order) and the table size.
 int tile_count();
+int device_cu_count();
 TileCfg tile_at(int i);
 
 // Autotuned choice for (n, precision): tile id and slots per CU (0 = not tuned).
