@@ -26,6 +26,9 @@ Parity status per function (see the pins in tests/test_oracle_*.py):
   half_gap               pinned: band-structure minimum over a dense k grid
   transmission_grad_bf   pinned: central finite differences
   transmission_grad      pinned: == transmission_grad_bf on tiny ribbons
+  ldos_bf                pinned: closed-form LDOS of the infinite 1D chain
+                         (the N = 2 ribbon), non-negativity
+  ldos                   pinned: == ldos_bf on tiny ribbons
 """
 
 from .rgf_oracle import (  # noqa: F401
@@ -38,6 +41,8 @@ from .rgf_oracle import (  # noqa: F401
     lead_self_energies,
     transmission,
     transmission_rl,
+    ldos,
+    ldos_bf,
     transmission_bf,
     transmission_grad,
     transmission_grad_bf,

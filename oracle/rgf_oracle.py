@@ -34,6 +34,8 @@ __all__ = [
     "transmission_bf",
     "transmission_grad",
     "transmission_grad_bf",
+    "ldos",
+    "ldos_bf",
     "open_channels",
     "half_gap",
     "transmission_sweep",
@@ -376,6 +378,58 @@ def transmission_grad(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
         F1i = G1s[i - 1] + F1i @ U.T @ gs[i - 1]
         d[i - 1] = 2.0 * np.real(np.einsum("ka,ab,bk->k", FiL, B, F1i))
     return T, d
+
+
+# --------------------------------------------------------------------------
+# Local density of states rho_s(E) = -Im G_ss(E) / pi: the diagonal of the
+# full Green's function G of Eq. (1) (the paper lists the charge density
+# among what the Green's function gives; the LDOS at energy E is its
+# spectral density).
+# --------------------------------------------------------------------------
+
+def ldos_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
+    """-Im diag(G) / pi as [L, N], from the full inverse (tiny ribbons only)."""
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    G = np.linalg.inv(_full_matrix(N, L, t, eta, E, eps, parity, sigmas))
+    return (-np.imag(np.diag(G)) / np.pi).reshape(L, N)
+
+
+def ldos(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
+    """-Im diag(G) / pi as [L, N] by the forward sweep of the left-connected
+    g_i (Eq. (4) form) and the backward recursion for the diagonal blocks of
+    the full Green's function, Dyson's equation (Eq. (3)) cut between slices
+    i and i+1:
+      F_{L,L} = g_L,   F_{i,i} = g_i + g_i U_i F_{i+1,i+1} U_i^T g_i.
+    """
+    z = complex(E, eta)
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    sig_l, sig_r = sigmas
+    Hs = _device_slices(N, L, t, eps)
+    eye = np.eye(N, dtype=np.complex128)
+    gs = []
+    A = z * eye - Hs[0] - sig_l
+    if L == 1:
+        A = A - sig_r
+    g = np.linalg.inv(A)
+    gs.append(g)
+    for j in range(2, L + 1):
+        U = coupling(N, t, j - 1, parity)
+        A = z * eye - Hs[j - 1] - U.T @ g @ U
+        if j == L:
+            A = A - sig_r
+        g = np.linalg.inv(A)
+        gs.append(g)
+    out = np.empty((L, N))
+    F = gs[-1]
+    out[L - 1] = -np.imag(np.diag(F)) / np.pi
+    for i in range(L - 1, 0, -1):   # slice i (1-based), python index i-1
+        U = coupling(N, t, i, parity)
+        gi = gs[i - 1]
+        F = gi + gi @ U @ F @ U.T @ gi
+        out[i - 1] = -np.imag(np.diag(F)) / np.pi
+    return out
 
 
 # --------------------------------------------------------------------------
