@@ -120,6 +120,24 @@ int rgf_grad(const rgf_ribbon_desc* desc, const double* energies_ev,
              double* dL_deps, int64_t ckpt_stride, int32_t* status_out,
              void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Local density of states of every device site s = (slice i, row k):
+ *   ldos_out[r][e][i][k] = -Im G_ss(E_e) / pi   (states per eV per site),
+ * the diagonal of the Green's function of Eq. (1), from Dyson's equation
+ * (Eq. (3)) applied backwards over the slices after the forward sweep of
+ * Eqs. (4)-(5) (the paper names the charge density among the quantities the
+ * Green's function gives; this is its spectral density at energy E).
+ *   ldos_out [n_real][n_energies][L][N]
+ *   T_out    [n_real][n_energies], or NULL
+ *   status_out [n_real][n_energies] int32, or NULL; a tuple that is not
+ *              RGF_TUPLE_OK gets NaN in all of its L*N entries.
+ * The workspace is the one rgf_grad uses: rgf_workspace_bytes(desc,
+ * n_energies, n_real, precision, want_grad = 1, ckpt_stride). */
+int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev,
+             int64_t n_energies, const double* onsite_eps_ev, int64_t n_real,
+             int precision, double* ldos_out, double* T_out, int64_t ckpt_stride,
+             int32_t* status_out, void* workspace, size_t workspace_bytes,
+             void* hip_stream);
+
 /* Several ribbons of different widths in one call (energy sweeps x disorder
  * realizations x widths). Ribbon d uses descs[d], its on-site energies at
  * onsite_eps_ev + eps_offsets[d] ([n_real][L_d][N_d]) and writes

@@ -12,6 +12,7 @@ from .rgf import (  # noqa: F401
     conductance,
     conductance_batched,
     grad,
+    ldos,
     RGFConductance,
     lead_self_energy,
     workspace_bytes,

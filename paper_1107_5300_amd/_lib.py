@@ -32,6 +32,7 @@ EXPORTED = (
     "rgf_workspace_bytes",
     "rgf_conductance",
     "rgf_grad",
+    "rgf_ldos",
     "rgf_batched_workspace_bytes",
     "rgf_conductance_batched",
     "rgf_lead_self_energy",
@@ -78,6 +79,9 @@ def _declare(lib):
     lib.rgf_grad.restype = _int
     lib.rgf_grad.argtypes = [_pdesc, _vp, _i64, _vp, _i64, _int, _vp, _vp, _vp, _i64, _vp,
                              _vp, _sz, _vp]
+    lib.rgf_ldos.restype = _int
+    lib.rgf_ldos.argtypes = [_pdesc, _vp, _i64, _vp, _i64, _int, _vp, _vp, _i64, _vp, _vp, _sz,
+                             _vp]
     lib.rgf_batched_workspace_bytes.restype = _sz
     lib.rgf_batched_workspace_bytes.argtypes = [_pdesc, _i32, _i64, _i64, _int]
     lib.rgf_conductance_batched.restype = _int

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librgf.so")
 
-SOURCES = ["rgf_api.cpp", "rgf_lead.hip", "rgf_forward.hip", "rgf_adjoint.hip"]
+SOURCES = ["rgf_api.cpp", "rgf_lead.hip", "rgf_forward.hip", "rgf_adjoint.hip", "rgf_ldos.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

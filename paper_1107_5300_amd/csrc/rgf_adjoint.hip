@@ -30,12 +30,6 @@ namespace rgf {
 
 namespace {
 
-template <int NW, int S, int C>
-__device__ __forceinline__ void copy_mat(cx<double>* dst, const cx<double>* src) {
-  constexpr int NP = NW * C;
-  for (int i = threadIdx.x; i < NP * NP; i += NW * 64) stg(dst + i, ldg(src + i));
-}
-
 template <typename TJ, bool REFINE, int NW, int S, int C>
 __global__ __launch_bounds__(NW * 64) void rgf_grad_kernel(SweepArgs a) {
   constexpr int NP = NW * C;
@@ -44,7 +38,7 @@ __global__ __launch_bounds__(NW * 64) void rgf_grad_kernel(SweepArgs a) {
   const int lane = lane_id(), w = wave_id();
   // slot: K0, G1, R, K1, Z, Q, X
   cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * MAT;
-  cx<double>* kb[2] = {slot, REFINE ? slot + 3 * MAT : slot};
+  cx<double>* const kb[2] = {slot, REFINE ? slot + 3 * MAT : slot};
   cx<double>* gbuf = slot + MAT;
   cx<double>* rbuf = slot + 2 * MAT;
   cx<double>* zbuf = slot + 4 * MAT;
@@ -65,16 +59,7 @@ __global__ __launch_bounds__(NW * 64) void rgf_grad_kernel(SweepArgs a) {
     cx<double> A[S][C];
 
     // ---- forward sweep with checkpoints of (g_h, G1_h) after every stride
-    for (int h = 0; h < H; ++h) {
-      half_step<TJ, REFINE, NW, S, C>(a, q, h, kb[(h + 1) & 1], kb[h & 1], gbuf, gbuf, rbuf,
-                                      A, sm);
-      if ((h + 1) % a.stride == 0 && h + 1 < H) {
-        cx<double>* c = ck + (size_t)((h + 1) / a.stride) * 2 * MAT;
-        copy_mat<NW, S, C>(c, kb[h & 1]);
-        copy_mat<NW, S, C>(c + MAT, gbuf);
-        __syncthreads();
-      }
-    }
+    forward_with_checkpoints<TJ, REFINE, NW, S, C>(a, q, kb, gbuf, rbuf, ck, A, sm);
     cx<double>* Klast = kb[(H - 1) & 1];
     const double T = trace_T<NW, S, C>(a, q, gbuf, xbuf, A, sm);  // S = Phi_L^T G Phi_R in A
     int st = a.lstat[q.e];
@@ -147,13 +132,7 @@ __global__ __launch_bounds__(NW * 64) void rgf_grad_kernel(SweepArgs a) {
       const int h0 = sgi * a.stride;
       const int h1 = min(H, h0 + a.stride);
       // recompute g_h, G1_h of the segment into sg
-      for (int h = h0; h < h1; ++h) {
-        const int j = h - h0;
-        const cx<double>* Kp = (j == 0) ? ck + (size_t)sgi * 2 * MAT : sg + (size_t)(j - 1) * 2 * MAT;
-        const cx<double>* Gp = Kp + MAT;
-        cx<double>* Ko = sg + (size_t)j * 2 * MAT;
-        half_step<TJ, REFINE, NW, S, C>(a, q, h, Kp, Ko, Gp, Ko + MAT, rbuf, A, sm);
-      }
+      recompute_segment<TJ, REFINE, NW, S, C>(a, q, sgi, h0, h1, ck, sg, rbuf, A, sm);
       // step Z and Q back through the segment; both are kept row-major
       // (X[r][c] at r*NP + c), so the matrix-core GEMMs read C_h X along rows
       // and write their results with contiguous columns

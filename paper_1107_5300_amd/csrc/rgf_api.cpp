@@ -261,6 +261,25 @@ int rgf_grad(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_e
   return RGF_OK;
 }
 
+int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_energies,
+             const double* onsite_eps_ev, int64_t n_real, int precision, double* ldos_out,
+             double* T_out, int64_t ckpt_stride, int32_t* status_out, void* workspace,
+             size_t workspace_bytes, void* hip_stream) {
+  Plan p;
+  int st = make_plan(desc, n_energies, n_real, precision, 1, ckpt_stride, &p);
+  if (st != RGF_OK) return st;
+  if (n_energies > 0) {
+    if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
+    if (!ldos_out) return fail(RGF_ERR_INVALID_ARG, "ldos_out is NULL");
+  }
+  st = check_ws(p, workspace, workspace_bytes);
+  if (st != RGF_OK) return st;
+  hipError_t e = launch_ldos(p, energies_ev, onsite_eps_ev, ldos_out, T_out, status_out,
+                             (char*)workspace, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return RGF_OK;
+}
+
 // Ribbons of several widths in one call: one persistent launch per ribbon
 // on the caller's stream, most expensive (N^3 L) first; the workspace is
 // reused from one launch to the next (stream order), so it is sized by the

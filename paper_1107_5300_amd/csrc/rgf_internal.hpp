@@ -78,6 +78,8 @@ int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad,
 
 // Kernel entry of the forward sweep / adjoint for a tile and precision.
 const void* fwd_kernel_ptr(const TileCfg& t, int precision);
+hipError_t launch_ldos(const Plan& p, const double* E, const double* eps, double* ldos,
+                       double* T_out, int32_t* status_out, char* ws, hipStream_t s);
 const void* grad_kernel_ptr(const TileCfg& t, int precision);
 
 // Matrix buffers (NP x NP complex128) per persistent slot.

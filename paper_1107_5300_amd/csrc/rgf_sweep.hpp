@@ -52,6 +52,8 @@ struct SweepArgs {
   cx<double>* ckpt;         // [grid][n_ckpt][2][NP*NP]
   cx<double>* seg;          // [grid][stride][2][NP*NP]
   int stride, n_ckpt;
+  // local density of states only
+  double* ldos;             // [nreal][nE][L][N]
 };
 
 template <int NW, int S, int C>
@@ -411,6 +413,51 @@ __device__ __forceinline__ double trace_T(const SweepArgs& a, const Tuple& q,
     }
   }
   return block_sum<NW>(part, sm.red);
+}
+
+// Forward sweep over all half-slices that also stores the restart state
+// (g_h, G1_h) after every `stride` half-slices into ck[1..] (the state at
+// h = 0 is rebuilt from the leads, so ck[0] stays unused). Used by the
+// reverse sweeps, which recompute each segment from its checkpoint. Leaves
+// g_{H-1} in kb[(H-1) & 1] and G1_{H-1} in gbuf.
+template <typename TJ, bool REFINE, int NW, int S, int C>
+__device__ __forceinline__ void forward_with_checkpoints(const SweepArgs& a, const Tuple& q,
+                                                         cx<double>* const (&kb)[2],
+                                                         cx<double>* gbuf, cx<double>* rbuf,
+                                                         cx<double>* ck, cx<double> (&A)[S][C],
+                                                         SweepSmem<NW, S, C>& sm) {
+  constexpr int NP = NW * C;
+  constexpr size_t MAT = (size_t)NP * NP;
+  const int H = 2 * a.L;
+  for (int h = 0; h < H; ++h) {
+    half_step<TJ, REFINE, NW, S, C>(a, q, h, kb[(h + 1) & 1], kb[h & 1], gbuf, gbuf, rbuf, A,
+                                    sm);
+    if ((h + 1) % a.stride == 0 && h + 1 < H) {
+      cx<double>* c = ck + (size_t)((h + 1) / a.stride) * 2 * MAT;
+      for (size_t i = threadIdx.x; i < MAT; i += NW * 64) {
+        stg(c + i, ldg(kb[h & 1] + i));
+        stg(c + MAT + i, ldg(gbuf + i));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Recompute g_h, G1_h for h0 <= h < h1 into the segment buffer sg (pairs of
+// matrices), starting from checkpoint sgi (or from the leads for sgi = 0).
+template <typename TJ, bool REFINE, int NW, int S, int C>
+__device__ __forceinline__ void recompute_segment(const SweepArgs& a, const Tuple& q, int sgi,
+                                                  int h0, int h1, cx<double>* ck, cx<double>* sg,
+                                                  cx<double>* rbuf, cx<double> (&A)[S][C],
+                                                  SweepSmem<NW, S, C>& sm) {
+  constexpr size_t MAT = (size_t)NW * C * NW * C;
+  for (int h = h0; h < h1; ++h) {
+    const int j = h - h0;
+    const cx<double>* Kp = (j == 0) ? ck + (size_t)sgi * 2 * MAT : sg + (size_t)(j - 1) * 2 * MAT;
+    const cx<double>* Gp = Kp + MAT;
+    cx<double>* Ko = sg + (size_t)j * 2 * MAT;
+    half_step<TJ, REFINE, NW, S, C>(a, q, h, Kp, Ko, Gp, Ko + MAT, rbuf, A, sm);
+  }
 }
 
 }  // namespace rgf

@@ -194,6 +194,41 @@ def grad(ribbon, energies, eps, dL_dT, precision="fp64", ckpt_stride=0, workspac
     return T, g
 
 
+def ldos(ribbon, energies, eps=None, n_real=1, precision="fp64", ckpt_stride=0,
+         workspace=None, return_T=False, return_status=False):
+    """Local density of states -Im G_ss(E)/pi of every site: [R, nE, L, N]
+    (states per eV per site), by the forward sweep and the backward sweep of
+    the diagonal blocks in librgf."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    if eps is not None:
+        if eps.dim() == 2:
+            eps = eps.unsqueeze(0)
+        _need(eps, "eps", (eps.shape[0], ribbon.L, ribbon.N))
+        n_real = eps.shape[0]
+    d = ribbon.desc()
+    L = _L.lib()
+    prec = _prec(precision)
+    nbytes = L.rgf_workspace_bytes(ctypes.byref(d), nE, int(n_real), prec, 1, int(ckpt_stride))
+    if nbytes == 0:
+        msg = L.rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    ws = _workspace(workspace, nbytes, dev)
+    out = torch.empty((int(n_real), nE, ribbon.L, ribbon.N), dtype=torch.float64, device=dev)
+    T = torch.empty((int(n_real), nE), dtype=torch.float64, device=dev)
+    st = torch.empty((int(n_real), nE), dtype=torch.int32, device=dev)
+    _L.check(L.rgf_ldos(ctypes.byref(d), _vp(energies), nE, _vp(eps), int(n_real), prec,
+                        _vp(out), _vp(T), int(ckpt_stride), _vp(st), _vp(ws), ws.numel(),
+                        _stream()))
+    res = (out,)
+    if return_T:
+        res += (T,)
+    if return_status:
+        res += (st,)
+    return res[0] if len(res) == 1 else res
+
+
 class RGFConductance(torch.autograd.Function):
     """T = RGFConductance.apply(eps, energies, ribbon, precision): conductance
     [R, nE] with a backward pass through the adjoint sweep (no gradient with
