@@ -1,5 +1,7 @@
 """Benchmark: RGF slice-steps/s of the armchair-ribbon conductance sweep on one
-MI355X, N=240 disordered ribbon (workload disorder_n240).
+MI355X, N=240 disordered ribbon (workload disorder_n240). `--row adjoint`,
+`--row batched` and `--row ldos` measure the gradient sweep, the
+mixed-width batched launch and the local density of states the same way.
 
 One step = one pass of the whole hot path over the workload: lead
 self-energies (Sancho-Rubio, FP64) + the slice recursion of every
@@ -291,7 +293,9 @@ def row_adjoint(args):
         "roofline": {"bound": "alu", "achieved": fl * steps / ev_s / 1e12,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": fl * steps / ev_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "rgf_grad_kernel", "tile": r["tile"],
+                     "kernel": "rgf_grad_kernel", "forward_tile_autotuned": r["tile"],
+                     "tile_note": "with no more tuples than compute units the sweep uses "
+                                  "the tiling with the most waves per tuple",
                      "flops_per_slice_step": fl, "event_ms_mean": ev_s * 1e3},
         "cpu_baseline": cpu,
         "accuracy": {"sampled_energies": sample, "max_abs_dT_vs_oracle": r["terr"],
@@ -300,6 +304,85 @@ def row_adjoint(args):
         "rates": {p: {"slice_steps_per_s": steps * args.steps / out[p]["wall"],
                       "max_abs_dT_vs_oracle": out[p]["terr"],
                       "max_rel_grad_err_vs_oracle": out[p]["derr"], "tile": out[p]["tile"]}
+                  for p in out},
+    }
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
+          flush=True)
+
+
+def _oracle_ldos_job(args):
+    n, l, E, eps = args
+    import oracle as O
+    return O.ldos(n, l, W.T_HOP, W.ETA, float(E), eps, 0)
+
+
+def row_ldos(args):
+    """Local density of states of every site, workload adjoint_n120's shape
+    (N=120, L=500, 128 energies, U[-0.3|t|, 0.3|t|]): one rgf_ldos call."""
+    import torch
+
+    import paper_1107_5300_amd as P
+    n, l = 120, 500
+    Es = W.energies("adjoint_n120")
+    eps = W.disorder(l, n, 0.3, r=0)
+    sample = [0, 37, 64, 101]
+    cpu, want = None, None
+    if not args.no_cpu:
+        jobs = [(n, l, Es[j], eps) for j in np.linspace(0, len(Es) - 1, 16).round().astype(int)]
+        _, wall_c, nw = _pool_map(_oracle_ldos_job, jobs)
+        cpu = {"value": len(jobs) * l / wall_c, "unit": "slice-steps/s (forward + LDOS sweep)",
+               "cores": nw, "kind": "oracle",
+               "sample": f"{len(jobs)} of {len(Es)} energies at full length, oracle forward + "
+                         f"backward diagonal sweep, one energy per process; {wall_c:.1f} s wall"}
+        want, _, _ = _pool_map(_oracle_ldos_job, [(n, l, Es[j], eps) for j in sample])
+        _say("ldos: oracle legs done")
+    dev = torch.device("cuda:0")
+    rib = P.Ribbon(n, l, 0, W.T_HOP, W.ETA)
+    E = torch.tensor(Es, device=dev)
+    ep = torch.tensor(eps[None], device=dev)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        tile = P.autotune(rib, prec)
+        ws = P.Workspace()
+        res = {}
+
+        def call():
+            res["rho"] = P.ldos(rib, E, ep, precision=prec, workspace=ws)
+        wall, ev = _events(torch, call, args.steps, args.warmup)
+        rho = res["rho"].cpu().numpy()[0]
+        err = None
+        if want is not None:
+            err = max(float(np.abs(rho[j] - w).max() / max(1.0, np.abs(w).max()))
+                      for j, w in zip(sample, want))
+        out[prec] = dict(wall=wall, ev=ev, err=err, tile=tile)
+        _say(f"ldos {prec}: {wall / args.steps:.3f} s per step")
+    ok = [p for p in out if out[p]["err"] is not None and out[p]["err"] <= GRAD_TOL] or list(out)
+    prec = min(ok, key=lambda p: out[p]["wall"])
+    r = out[prec]
+    steps = len(Es) * l
+    ev_s = float(np.mean(r["ev"])) / 1e3
+    fl = 3 * flops_per_slice_step(n)
+    line = {
+        "metric": "LDOS RGF slice-steps/s (forward + diagonal sweep) at N=120",
+        "value": steps * args.steps / r["wall"], "unit": "slice-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall"] / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed": "f32+f64"}[prec], "data": "synthetic",
+        "config": {"workload": "adjoint_n120 shape, LDOS of all 60,000 sites", "N": n, "L": l,
+                   "n_energies": len(Es), "n_real": 1, "precision": prec,
+                   "slice_steps_per_step": steps},
+        "roofline": {"bound": "alu", "achieved": fl * steps / ev_s / 1e12,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fl * steps / ev_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "rgf_ldos_kernel", "forward_tile_autotuned": r["tile"],
+                     "tile_note": "with no more tuples than compute units the sweep uses "
+                                  "the tiling with the most waves per tuple",
+                     "flops_per_slice_step": fl, "event_ms_mean": ev_s * 1e3},
+        "cpu_baseline": cpu,
+        "accuracy": {"sampled_energies": sample,
+                     "max_rel_ldos_err_vs_oracle": r["err"], "bar_rel": GRAD_TOL},
+        "rates": {p: {"slice_steps_per_s": steps * args.steps / out[p]["wall"],
+                      "max_rel_ldos_err_vs_oracle": out[p]["err"], "tile": out[p]["tile"]}
                   for p in out},
     }
     print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
@@ -394,9 +477,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--row", default="main", choices=["main", "adjoint", "batched"],
+    ap.add_argument("--row", default="main", choices=["main", "adjoint", "batched", "ldos"],
                     help="main: the N=240 sweep (the metric); adjoint: gradient sweep of the "
-                         "N=120 workload; batched: the mixed-width batched launch")
+                         "N=120 workload; batched: the mixed-width batched launch; ldos: "
+                         "local density of states of the N=120 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -407,6 +491,8 @@ def main():
         return row_adjoint(args)
     if args.row == "batched":
         return row_batched(args)
+    if args.row == "ldos":
+        return row_ldos(args)
 
     Es = W.energies(WORKLOAD)
     eps = W.disorder(L, N, WDIS, r=0)
