@@ -42,7 +42,8 @@ def test_version_and_strings():
 
 
 @pytest.mark.parametrize("field,value,code", [
-    ("width_n", 1, -1), ("width_n", 100000, -4), ("length_l", 0, -1), ("parity", 2, -1),
+    ("width_n", 1, -1), ("width_n", 100000, -4), ("width_n", 480, -4), ("width_n", 257, -4),
+    ("length_l", 0, -1), ("parity", 2, -1),
     ("hopping_ev", 0.0, -1), ("hopping_ev", float("nan"), -1), ("eta_ev", 0.0, -1),
     ("eta_ev", -1e-8, -1), ("eta_ev", float("inf"), -1), ("struct_size", 8, -1),
 ])
@@ -120,3 +121,21 @@ def test_forward_kernels_use_no_scratch():
     assert len(fwd) >= 20, "report lists too few forward kernels"
     bad = [(r[0], r[3], r[4]) for r in fwd if r[3] != "0" or r[4] != "0"]
     assert not bad, f"forward kernels with scratch / VGPR spills: {bad}"
+
+
+def test_widest_supported_and_first_unsupported_width():
+    """n = ceil(N/2) must fit the register tiling (n <= 128): N = 256 plans,
+    N = 257 and the N = 480 workload report RGF_ERR_UNSUPPORTED for every
+    sweep entry point, before anything is enqueued."""
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    ok = L.make_desc(256, 4)
+    assert lib.rgf_workspace_bytes(ctypes.byref(ok), 4, 1, 0, 0, 0) > 0
+    assert lib.rgf_workspace_bytes(ctypes.byref(ok), 4, 1, 0, 1, 0) > 0
+    for N in (257, 480):
+        d = L.make_desc(N, 4)
+        assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 0, 0) == 0
+        rc = lib.rgf_ldos(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+                          ctypes.c_void_p(16), None, 0, None, None, 0, None)
+        assert rc == L.RGF_ERR_UNSUPPORTED
+        assert b"outside [2, 256]" in lib.rgf_last_error_message()
