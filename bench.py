@@ -1,7 +1,8 @@
 """Benchmark: RGF slice-steps/s of the armchair-ribbon conductance sweep on one
 MI355X, N=240 disordered ribbon (workload disorder_n240). `--row adjoint`,
-`--row batched` and `--row ldos` measure the gradient sweep, the
-mixed-width batched launch and the local density of states the same way.
+`--row batched`, `--row ldos` and `--row wide` measure the gradient sweep,
+the mixed-width batched launch, the local density of states and the N=480
+ribbon (blocked half-slice inversion) the same way.
 
 One step = one pass of the whole hot path over the workload: lead
 self-energies (Sancho-Rubio, FP64) + the slice recursion of every
@@ -464,6 +465,86 @@ def row_batched(args):
           flush=True)
 
 
+def _oracle_sweep_timing_job(args):
+    """Oracle slice recursion of one energy on the first `ls` slices of the
+    wide ribbon, timed; the lead self-energies are set to zero (the dense
+    decimation of a 960-site cell would dominate the sample, and the
+    recursion's cost does not depend on their values). Timing only."""
+    n, ls, E, eps = args
+    import oracle as O
+    z = np.zeros((n, n), dtype=np.complex128)
+    t0 = time.perf_counter()
+    O.transmission(n, ls, W.T_HOP, W.ETA, float(E), eps[:ls], 0, sigmas=(z, z))
+    return time.perf_counter() - t0
+
+
+def row_wide(args):
+    """Ribbons wider than one register tile, workload large_n480 (N = 480,
+    L = 8000, U[-0.5|t|, 0.5|t|]) at every 4th of its 1024 energies, FP64:
+    one rgf_conductance call through the blocked (2 x 2 Schur) inversion."""
+    import torch
+
+    import paper_1107_5300_amd as P
+    cfg = W.WORKLOADS["large_n480"]
+    n, l = cfg["N"][0], cfg["L"]
+    Es = W.energies("large_n480")[::4]
+    eps = W.disorder(l, n, cfg["w"], r=0)
+    golden = np.atleast_2d(np.loadtxt(os.path.join(ROOT, "tests", "golden",
+                                                   "large_n480_sampled.txt")))
+    cpu = None
+    if not args.no_cpu:
+        ls = 500
+        jobs = [(n, ls, Es[j], eps) for j in np.linspace(0, len(Es) - 1, 16).round().astype(int)]
+        per, wall_c, nw = _pool_map(_oracle_sweep_timing_job, jobs)
+        cpu = {"value": len(jobs) * ls / wall_c, "unit": "slice-steps/s", "cores": nw,
+               "kind": "oracle",
+               "sample": f"{len(jobs)} energies x the first {ls} slices of the N={n} ribbon, "
+                         f"oracle recursion only (lead self-energies set to zero, timing only), "
+                         f"one energy per process; {wall_c:.1f} s wall"}
+        _say(f"wide: cpu sample {wall_c:.1f} s")
+    dev = torch.device("cuda:0")
+    rib = P.Ribbon(n, l, 0, W.T_HOP, W.ETA)
+    E = torch.tensor(Es, device=dev)
+    ep = torch.tensor(eps[None], device=dev)
+    ws = P.Workspace()
+    res = {}
+
+    def call():
+        res["T"] = P.conductance(rib, E, ep, workspace=ws)
+        torch.cuda.synchronize()   # one call takes tens of seconds: report each
+        _say("wide: one call done")
+    wall, ev = _events(torch, call, args.steps, args.warmup)
+    T, st = P.conductance(rib, E, ep, workspace=ws, return_status=True)
+    torch.cuda.synchronize()
+    T, st = T.cpu().numpy()[0], st.cpu().numpy()[0]
+    errs = {int(j): float(abs(T[int(j) // 4] - v)) for j, _, v in golden if int(j) % 4 == 0}
+    _say(f"wide: {wall / args.steps:.2f} s per step, |dT| {errs}")
+    steps = len(Es) * l
+    ev_s = float(np.mean(ev)) / 1e3
+    fl = flops_per_slice_step(n) * steps
+    line = {
+        "metric": "RGF slice-steps/s at N=480 (blocked half-slice inversion), FP64",
+        "value": steps * args.steps / wall, "unit": "slice-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "large_n480 (256 of 1024 energies)", "N": n, "L": l,
+                   "n_energies": len(Es), "n_real": 1, "precision": "fp64",
+                   "slice_steps_per_step": steps},
+        "roofline": {"bound": "alu", "achieved": fl / ev_s / 1e12, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": fl / ev_s / 1e12 / PEAK_FP64_TFLOPS,
+                     "traffic": None, "kernel": "rgf_fwd_large_kernel",
+                     "flops_per_slice_step": flops_per_slice_step(n),
+                     "event_ms_mean": ev_s * 1e3},
+        "cpu_baseline": cpu,
+        "accuracy": {"stored_oracle_energies": sorted(errs), "max_abs_dT_vs_oracle":
+                     max(errs.values()) if errs else None, "bar": ACC_TOL,
+                     "tuples_not_ok": int((st != 0).sum())},
+    }
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -477,10 +558,12 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--row", default="main", choices=["main", "adjoint", "batched", "ldos"],
+    ap.add_argument("--row", default="main",
+                    choices=["main", "adjoint", "batched", "ldos", "wide"],
                     help="main: the N=240 sweep (the metric); adjoint: gradient sweep of the "
                          "N=120 workload; batched: the mixed-width batched launch; ldos: "
-                         "local density of states of the N=120 workload")
+                         "local density of states of the N=120 workload; wide: the N=480 "
+                         "workload through the blocked half-slice inversion")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -493,6 +576,8 @@ def main():
         return row_batched(args)
     if args.row == "ldos":
         return row_ldos(args)
+    if args.row == "wide":
+        return row_wide(args)
 
     Es = W.energies(WORKLOAD)
     eps = W.disorder(L, N, WDIS, r=0)

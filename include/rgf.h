@@ -48,7 +48,7 @@ extern "C" {
 #endif
 
 #define RGF_ABI_VERSION_MAJOR 1
-#define RGF_ABI_VERSION_MINOR 0
+#define RGF_ABI_VERSION_MINOR 1
 
 /* Ribbon geometry and model constants. */
 typedef struct {
@@ -60,7 +60,17 @@ typedef struct {
   double eta_ev;        /* eta > 0 and finite (e.g. 1e-8)                     */
 } rgf_ribbon_desc;
 
-#define RGF_MAX_WIDTH 256
+#define RGF_MAX_WIDTH 512
+
+/* Widths up to RGF_TILE_MAX_WIDTH keep each half-slice (ceil(N/2) rows) in
+ * one workgroup's registers and support every entry point and precision.
+ * Wider ribbons (RGF_TILE_MAX_WIDTH < N <= RGF_MAX_WIDTH) invert each
+ * half-slice by 2 x 2 blocks (Schur complement) and support the FP64
+ * conductance only: rgf_conductance, rgf_conductance_batched,
+ * rgf_lead_self_energy and rgf_autotune (nothing to tune) with
+ * RGF_PREC_FP64; rgf_grad, rgf_ldos and the FP32 modes return
+ * RGF_ERR_UNSUPPORTED for them. */
+#define RGF_TILE_MAX_WIDTH 256
 
 /* Arithmetic of the slice recursion. The lead self-energies, the running
  * propagator G_1i and the trace are FP64 in every mode. */
@@ -83,7 +93,13 @@ enum {
   RGF_TUPLE_OK = 0,
   RGF_TUPLE_NO_CONVERGENCE = 1, /* lead decimation hit its iteration cap     */
   RGF_TUPLE_SINGULAR = 2,       /* exact zero pivot in a slice inversion     */
-  RGF_TUPLE_NONFINITE = 3       /* T came out NaN or Inf                     */
+  RGF_TUPLE_NONFINITE = 3,      /* T came out NaN or Inf                     */
+  RGF_TUPLE_OUT_OF_RANGE = 4    /* T outside [0, number of lead modes]: the
+                                   recursion lost its accuracy. Seen at E = 0
+                                   exactly when on-site energies vanish: each
+                                   half-slice is then one sublattice with no
+                                   diagonal term, and its left-connected
+                                   Green's function grows like 1/eta      */
 };
 
 /* Bytes of device workspace the call with the same arguments needs.

@@ -26,6 +26,7 @@ TUPLE_OK = 0
 TUPLE_NO_CONVERGENCE = 1
 TUPLE_SINGULAR = 2
 TUPLE_NONFINITE = 3
+TUPLE_OUT_OF_RANGE = 4
 
 # every symbol declared in include/rgf.h
 EXPORTED = (

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librgf.so")
 
-SOURCES = ["rgf_api.cpp", "rgf_lead.hip", "rgf_forward.hip", "rgf_adjoint.hip", "rgf_ldos.hip"]
+SOURCES = ["rgf_api.cpp", "rgf_lead.hip", "rgf_forward.hip", "rgf_adjoint.hip", "rgf_ldos.hip",
+           "rgf_large.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
@@ -131,7 +132,7 @@ def build(verbose=False, jobs=None, incremental=False):
         msg = "\n".join(f"--- {s}\n{t}" for s, t in failed)
         raise RuntimeError("HIP build failed:\n" + msg)
     tmp = LIB + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)

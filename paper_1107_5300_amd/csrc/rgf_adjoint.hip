@@ -65,6 +65,7 @@ __global__ __launch_bounds__(NW * 64) void rgf_grad_kernel(SweepArgs a) {
     int st = a.lstat[q.e];
     if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
     if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
+    if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
     if (threadIdx.x == 0) {
       a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
       if (a.status) a.status[tau] = st;

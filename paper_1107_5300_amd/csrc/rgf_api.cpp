@@ -89,9 +89,24 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   q.ntuples = nE * nreal;
   q.precision = precision;
   q.want_grad = want_grad != 0;
-  if (!pick_tile(q.nmax, precision, &q.tile))
+  q.large = q.nmax > kTileMaxRows;
+  if (q.large) {
+    // half-slices wider than one register tile: blocked inversion, FP64
+    // conductance only
+    if (precision != RGF_PREC_FP64)
+      return fail(RGF_ERR_UNSUPPORTED,
+                  "width_n = %d: half-slices above %d rows run in FP64 only", q.N,
+                  kTileMaxRows);
+    if (q.want_grad)
+      return fail(RGF_ERR_UNSUPPORTED,
+                  "width_n = %d: the reverse sweeps support half-slices of at most %d rows "
+                  "(width_n <= %d)",
+                  q.N, kTileMaxRows, 2 * kTileMaxRows);
+    q.tile = large_block_tile();
+  } else if (!pick_tile(q.nmax, precision, &q.tile)) {
     return fail(RGF_ERR_UNSUPPORTED, "width_n = %d exceeds the register tiling", q.N);
-  if (q.want_grad && q.ntuples <= device_cu_count()) {
+  }
+  if (!q.large && q.want_grad && q.ntuples <= device_cu_count()) {
     // Fewer tuples than compute units: each workgroup runs one tuple at a
     // time and the sweep is latency-bound, so prefer the tiling with the
     // most waves per tuple among those that pad n by at most a quarter.
@@ -105,19 +120,25 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
     q.tile = best;
   }
   const int NP = q.tile.NP();
-  {
+  if (q.large) {
+    q.grid = persistent_grid_large(std::max<int64_t>(q.ntuples, 1));
+    q.slot_elems = (int64_t)kTileMaxRows * kTileMaxRows;
+    q.slot_mats = large_slot_blocks();
+    q.phi_ld = kLargeLd;
+  } else {
     int tid = 0, per_cu = 0;
     if (!q.want_grad && tuned_choice(q.nmax, precision, &tid, &per_cu)) q.per_cu = per_cu;
+    q.grid = persistent_grid(q.tile, std::max<int64_t>(q.ntuples, 1), precision, q.want_grad,
+                             q.per_cu);
+    q.slot_elems = (int64_t)NP * NP;
+    q.slot_mats = slot_matrices(precision, q.want_grad);
+    q.phi_ld = NP;
   }
-  q.grid = persistent_grid(q.tile, std::max<int64_t>(q.ntuples, 1), precision, q.want_grad,
-                           q.per_cu);
-  q.slot_elems = (int64_t)NP * NP;
-  q.slot_mats = slot_matrices(precision, q.want_grad);
   size_t off = 0;
   q.off_sigma = off;
   off = align_up(off + (size_t)nE * q.P * 16, 256);
   q.off_phi = off;
-  off = align_up(off + (size_t)2 * q.P * NP * 8, 256);
+  off = align_up(off + (size_t)2 * q.P * q.phi_ld * 8, 256);
   q.off_lstat = off;
   off = align_up(off + (size_t)nE * 4, 256);
   q.off_status = off;
@@ -188,6 +209,28 @@ int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad,
     (void)hipGetLastError();
   }
   if (per_cu > 0 && per_cu < occ) occ = per_cu;
+  int64_t g = (int64_t)ncu * occ;
+  if (g > ntuples) g = ntuples;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int persistent_grid_large(int64_t ntuples) {
+  int dev = 0, ncu = 256, occ = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, large_kernel_ptr(),
+                                                     large_block_tile().threads(), 0) ==
+            hipSuccess &&
+        o > 0)
+      occ = o;
+    else
+      (void)hipGetLastError();
+  } else {
+    (void)hipGetLastError();
+  }
   int64_t g = (int64_t)ncu * occ;
   if (g > ntuples) g = ntuples;
   if (g < 1) g = 1;
@@ -374,7 +417,9 @@ int tune_plan(const rgf_ribbon_desc* desc, int precision, rgf_ribbon_desc* dd,
   else
     (void)hipGetLastError();
   ts->nE = (int64_t)ncu * 4;  // enough tuples for every grid size tried
-  (void)precision;
+  if ((desc->width_n + 1) / 2 > kTileMaxRows && precision != RGF_PREC_FP64)
+    return fail(RGF_ERR_UNSUPPORTED, "width_n = %d: half-slices above %d rows run in FP64 only",
+                desc->width_n, kTileMaxRows);
   return RGF_OK;
 }
 
@@ -422,6 +467,15 @@ int rgf_autotune(const rgf_ribbon_desc* desc, int precision, void* workspace,
     return fail(RGF_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
   if (!workspace || ((uintptr_t)workspace) % 256 != 0)
     return fail(RGF_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if ((dd.width_n + 1) / 2 > kTileMaxRows) {
+    // one blocked kernel serves every width above the register tilings:
+    // nothing to choose
+    if (chosen_out) {
+      const TileCfg t = large_block_tile();
+      *chosen_out = t.NW * 10000 + t.S * 1000 + t.C * 10;
+    }
+    return RGF_OK;
+  }
   hipStream_t s = (hipStream_t)hip_stream;
   char* base = (char*)workspace;
   double* E = (double*)base;

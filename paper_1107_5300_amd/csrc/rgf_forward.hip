@@ -45,6 +45,7 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_f
       int st = a.lstat[q.e];
       if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
       if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
+      if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
       a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
       if (a.status) a.status[tau] = st;
     }
@@ -109,6 +110,7 @@ const void* fwd_kernel_ptr(const TileCfg& t, int precision) {
 
 hipError_t launch_forward(const Plan& p, const double* E, const double* eps, double* T_out,
                           int32_t* status_out, char* ws, hipStream_t s) {
+  if (p.large) return launch_forward_large(p, E, eps, T_out, status_out, ws, s);
   if (p.ntuples == 0) return hipSuccess;
   hipError_t err = launch_lead(p, E, ws, s);
   if (err != hipSuccess) return err;

@@ -36,6 +36,12 @@ void set_tuned_choice(int n, int precision, int tile_id, int per_cu);
 // odd N).
 inline int lead_modes(int N) { return (N + 1) / 2; }
 
+// Half-slices wider than the widest register tiling (n > kTileMaxRows) take
+// the blocked path of rgf_large.hip: matrices in the workspace with leading
+// dimension kLargeLd, inverted by panels, FP64 forward only.
+constexpr int kTileMaxRows = 128;
+constexpr int kLargeLd = 256;
+
 // Byte layout of one call's workspace.
 struct Plan {
   int N, L, parity, P, n1, nmax;
@@ -52,6 +58,8 @@ struct Plan {
       total;
   int64_t ckpt_stride, n_ckpt;
   bool want_grad;
+  bool large;   // blocked path (n > kTileMaxRows)
+  int phi_ld;   // leading dimension of the lead mode tables
 };
 
 // Fill the plan; returns RGF_OK or an error code (with message set).
@@ -75,6 +83,8 @@ hipError_t launch_grad(const Plan& p, const double* E, const double* eps,
 // Persistent grid size for a tile config on the current device.
 int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad,
                     int per_cu = 0);
+// The same for the blocked wide-half-slice kernel.
+int persistent_grid_large(int64_t ntuples);
 
 // Kernel entry of the forward sweep / adjoint for a tile and precision.
 const void* fwd_kernel_ptr(const TileCfg& t, int precision);
@@ -84,5 +94,15 @@ const void* grad_kernel_ptr(const TileCfg& t, int precision);
 
 // Matrix buffers (NP x NP complex128) per persistent slot.
 int slot_matrices(int precision, bool grad);
+
+// Blocked forward sweep for kTileMaxRows < n <= kLargeLd (FP64).
+hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
+                                double* T_out, int32_t* status_out, char* ws, hipStream_t s);
+const void* large_kernel_ptr();
+// Register tiling of the blocked kernel's elimination panels (id -1: not a
+// table entry), and its buffers per slot in units of kTileMaxRows^2
+// complex128.
+TileCfg large_block_tile();
+int large_slot_blocks();
 
 }  // namespace rgf

@@ -1,0 +1,441 @@
+// rgf_large.hip -- the forward sweep for half-slices wider than one
+// workgroup's register tile: 128 < n <= 256 (256 < N <= 512), FP64.
+//
+// The recursion is the one of rgf_sweep.hpp (Eqs. (4)-(5) on the half-slice
+// chain); only the inversion of M_h changes. An n = 240 complex128 matrix
+// (921 KB) exceeds one compute unit's registers and LDS, so M_h lives in the
+// workspace and is inverted by Gauss-Jordan in column panels of width
+// b = 64, keeping partial pivoting over the full height:
+//
+//   * the panel (all n rows x b columns, already transformed by the earlier
+//     panels) is loaded into registers (lane l: rows l + 64 s, s < 4; wave
+//     w: columns 8 w .. 8 w + 7) and eliminated in place there, the pivot of
+//     each column chosen among all rows not yet used by any panel;
+//   * the b steps act on every other column v as one linear map,
+//     v <- v + W v_P, with P the panel's pivot rows and W = Z - E_P (Z the
+//     panel after elimination, E_P the unit columns of its pivot rows), so
+//     the other n - b columns take one rank-b update on the matrix cores
+//     (the pivot rows are staged first: the update rewrites them);
+//   * after the last panel the array holds the inverse with its rows and
+//     columns permuted by the pivot order, as in the in-register version,
+//     and is written out un-permuted.
+//
+// Pivoting across the whole height matters: a 2 x 2 block (Schur
+// complement) inversion without it is unstable here. The principal blocks
+// of M_h are nonsingular (Im M_h is positive definite) but can be
+// arbitrarily ill-conditioned when eta is small, e.g. for evanescent modes
+// inside a subband gap.
+//
+// Workspace per persistent workgroup, complex128, leading dimension LD = 256
+// (column-major): K (g_h), G1 ping-pong x 2, X (the matrix being inverted),
+// Y (trace scratch), and Xp (the staged pivot rows, b x LD row-major).
+// g_h is complex symmetric, so it is read in whichever order is contiguous.
+
+#include <string.h>
+
+#include "rgf_sweep.hpp"
+
+namespace rgf {
+
+namespace {
+
+constexpr int LD = kLargeLd;               // leading dimension of the full matrices
+constexpr int BW = 8, BS = 4, BC = 8;      // panel register tile: 256 rows x 64 columns
+constexpr int NR = 64 * BS, PB = BW * BC;  // rows held, panel width
+constexpr int BP = kTileMaxRows;           // output block of the GEMM calls
+static_assert(NR == LD && 2 * BP == LD, "panel height and GEMM blocks");
+constexpr int kSlotBlocks = 5 * 4 + 1;     // K, G1 x 2, X, Y (4 blocks each); Xp
+static_assert(PB * LD <= BP * BP, "the staged pivot rows fit one block");
+
+struct LargeSmem {
+  cx<double> colbuf[2 * (NR + 1)];  // pivot column and 1/pivot, double-buffered
+  int pivrow[NR];                   // pivot row of each elimination step
+  int pinv[NR];
+  double red[2 * BW];
+  int flag;
+};
+
+// ---------------------------------------------------------------- panel GJ
+// The elimination step of rgf_engine.hpp on a tall panel: rows up to NR,
+// BW*BC columns, steps 0..nsteps-1 of the panel (the caller passes the
+// panel's slice of the pivot list), pivot candidates the rows r < n not yet
+// used.
+
+// A[s][J] for a uniform-per-lane slot s: one branch per slot, kept apart
+// by a distinct empty asm statement, so the tile is never indexed
+// dynamically (a select chain over four slots is folded into a dynamic
+// index, which moves the whole tile to scratch memory).
+template <int J, int SS = 0>
+__device__ __forceinline__ cx<double> pick_slot_br(const cx<double> (&A)[BS][BC], int s) {
+  if constexpr (SS + 1 < BS) {
+    if (s == SS) {
+      asm volatile("; pick slot %0" ::"n"(SS));
+      return A[SS][J];
+    }
+    return pick_slot_br<J, SS + 1>(A, s);
+  } else {
+    return A[SS][J];
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void pgj_select_pivot(const cx<double> (&A)[BS][BC], int kc, int n,
+                                                 uint32_t used, cx<double>* colbuf, int* pivrow,
+                                                 int* flag) {
+  const int lane = lane_id();
+  cx<double>* cb = colbuf + (kc & 1) * (NR + 1);
+  uint32_t key = 0u;
+#pragma unroll
+  for (int s = 0; s < BS; ++s) {
+    const int r = lane + 64 * s;
+    cb[r] = A[s][J];
+    key = max(key, pivot_key(A[s][J], r, r < n && !((used >> s) & 1u)));
+  }
+  key = wave_max_u32(key);
+  const int pk = 255 - (int)(key & 0xFFu);
+  if (lane == (pk & 63)) {
+    const cx<double> pv = pick_slot_br<J>(A, pk >> 6);
+    pivrow[kc] = pk;
+    cb[NR] = crcp_scaled(pv);
+    if (!(cabs1(pv) > 0.0)) *flag = 1;
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void pgj_step(cx<double> (&A)[BS][BC], int kb, int nsteps, int n,
+                                         uint32_t& used, cx<double>* colbuf, int* pivrow,
+                                         int* flag) {
+  constexpr int JN = (J + 1) % BC;
+  const int lane = lane_id(), w = wave_id();
+  const int k = kb * BC + J;
+  const int kbn = (J + 1 == BC) ? kb + 1 : kb;
+  __syncthreads();
+  const cx<double>* cb = colbuf + (k & 1) * (NR + 1);
+  const int pkr = pivrow[k];
+  const cx<double> ipiv = cb[NR];
+  cx<double> a[BS];
+#pragma unroll
+  for (int s = 0; s < BS; ++s) a[s] = cb[lane + 64 * s];
+  __builtin_amdgcn_sched_barrier(0);
+  const int pk = __builtin_amdgcn_readfirstlane(min(max(pkr, 0), NR - 1));
+  const int pl = pk & 63, ps = pk >> 6;
+  cx<double> m[BS];
+#pragma unroll
+  for (int s = 0; s < BS; ++s) {
+    const int r = lane + 64 * s;
+    m[s] = (r == pk) ? mk(1.0 - ipiv.re, -ipiv.im) : cmul(a[s], ipiv);
+  }
+  if (lane == pl) used |= 1u << ps;
+  const bool own = (w == kb);
+  {
+    cx<double> v1[1];
+    gj_row_chunk<double, BS, BC, JN, 1, -1, 0>(A, ps, pl, v1);
+    gj_update_column<double, BS, BC, JN>(A, m, v1[0]);
+  }
+  if (w == kbn && k + 1 < nsteps)
+    pgj_select_pivot<JN>(A, k + 1, n, used, colbuf, pivrow, flag);
+  gj_update_chunks<double, BS, BC, J, JN, 0>(A, m, ps, pl, own);
+}
+
+template <int J>
+__device__ __forceinline__ void pgj_block(cx<double> (&A)[BS][BC], int kb, int nsteps, int n,
+                                          uint32_t& used, cx<double>* colbuf, int* pivrow,
+                                          int* flag) {
+  if constexpr (J < BC) {
+    if (kb * BC + J >= nsteps) return;
+    pgj_step<J>(A, kb, nsteps, n, used, colbuf, pivrow, flag);
+    pgj_block<J + 1>(A, kb, nsteps, n, used, colbuf, pivrow, flag);
+  }
+}
+
+__device__ __forceinline__ void pgj_panel(cx<double> (&A)[BS][BC], int nsteps, int n,
+                                          uint32_t& used, LargeSmem& sm, int c0) {
+  int* pivrow = sm.pivrow + c0;
+  if (nsteps > 0 && wave_id() == 0)
+    pgj_select_pivot<0>(A, 0, n, used, sm.colbuf, pivrow, &sm.flag);
+  for (int kb = 0; kb < BW; ++kb) {
+    if (kb * BC >= nsteps) break;
+    pgj_block<0>(A, kb, nsteps, n, used, sm.colbuf, pivrow, &sm.flag);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- sweep
+
+// M_h (n x n) into X, column-major; returns the largest |re| + |im| of the
+// thread's entries (NaN if any is NaN).
+__device__ __forceinline__ double build_M_large(const SweepArgs& a, const Tuple& q, int h,
+                                                const cx<double>* K, cx<double>* X) {
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  const int nL = half_size(a.N, e ^ 1);
+  const bool rhalf = (h & 1) != 0;
+  const double mt2 = -(a.t * a.t);
+  const double* eps = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
+  const double* ph = (h == 0) ? a.phi : (h == 2 * a.L - 1) ? a.phi + (size_t)a.P * LD : nullptr;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n * n; i += BW * 64) {
+    const int c = i / n, r = i - c * n;
+    cx<double> v = mk(0.0, 0.0);
+    if (h > 0) {
+      if (!rhalf) {
+        v = cscale(ldg(K + (size_t)c * LD + r), mt2);
+      } else {
+        const int r0 = nb_lo(r, e), r1 = nb_hi(r, e), c0 = nb_lo(c, e), c1 = nb_hi(c, e);
+        cx<double> acc = mk(0.0, 0.0);
+        if (c0 >= 0) {
+          if (r0 >= 0) acc = cadd(acc, ldg(K + (size_t)c0 * LD + r0));
+          if (r1 < nL) acc = cadd(acc, ldg(K + (size_t)c0 * LD + r1));
+        }
+        if (c1 < nL) {
+          if (r0 >= 0) acc = cadd(acc, ldg(K + (size_t)c1 * LD + r0));
+          if (r1 < nL) acc = cadd(acc, ldg(K + (size_t)c1 * LD + r1));
+        }
+        v = cscale(acc, mt2);
+      }
+    }
+    if (r == c) v = cadd(v, mk(q.z.re - (eps ? eps[half_row(r, e)] : 0.0), q.z.im));
+    if (ph) {  // lead self-energy on the first and the last half-slice
+      for (int p = 0; p < a.P; ++p) {
+        const double f = ph[(size_t)p * LD + r] * ph[(size_t)p * LD + c];
+        v.re = fma(-f, q.sig[p].re, v.re);
+        v.im = fma(-f, q.sig[p].im, v.im);
+      }
+    }
+    const double m1 = cabs1(v);
+    mx = (m1 > mx || m1 != m1) ? m1 : mx;
+    stg(X + (size_t)c * LD + r, v);
+  }
+  return mx;
+}
+
+// 2^-e with mx in [2^(e-1), 2^e) (1 for a zero or non-finite maximum).
+__device__ __forceinline__ double pow2_scale(double mx) {
+  if (!(mx > 0.0) || !isfinite(mx)) return 1.0;
+  int ex = 0;
+  (void)frexp(mx, &ex);
+  return ldexp(1.0, min(-ex, 1022));
+}
+
+// g = M^{-1} (M in X, n x n) into K by the panel Gauss-Jordan; f is the
+// power-of-two scale applied to M for the elimination.
+__device__ __forceinline__ void invert_panels(int n, double f, cx<double>* X, cx<double>* Xp,
+                                              cx<double>* K, cx<double> (&A)[BS][BC],
+                                              LargeSmem& sm) {
+  const int lane = lane_id(), w = wave_id();
+  uint32_t used = 0u;
+  for (int c0 = 0; c0 < n; c0 += PB) {
+    const int bw = min(PB, n - c0);
+    const double fs = (c0 == 0) ? f : 1.0;  // the first panel applies the scale
+    // load the panel (rows >= n and columns >= bw stay zero)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) {
+      const int c = w * BC + j;
+#pragma unroll
+      for (int s = 0; s < BS; ++s) {
+        const int r = lane + 64 * s;
+        A[s][j] = (r < n && c < bw) ? cscale(ldg(X + (size_t)(c0 + c) * LD + r), fs)
+                                    : mk(0.0, 0.0);
+      }
+    }
+    pgj_panel(A, bw, n, used, sm, c0);
+    // the panel after elimination back to X
+#pragma unroll
+    for (int j = 0; j < BC; ++j) {
+      const int c = w * BC + j;
+      if (c >= bw) break;
+#pragma unroll
+      for (int s = 0; s < BS; ++s) {
+        const int r = lane + 64 * s;
+        if (r < n) stg(X + (size_t)(c0 + c) * LD + r, A[s][j]);
+      }
+    }
+    const int nother = n - bw;
+    if (nother > 0) {
+      // stage the pivot rows of the other columns: Xp[j][c] = fs * X[P_j][c]
+      for (int i = threadIdx.x; i < bw * n; i += BW * 64) {
+        const int j = i / n, c = i - j * n;
+        if (c >= c0 && c < c0 + bw) continue;
+        stg(Xp + (size_t)j * LD + c, cscale(ldg(X + (size_t)c * LD + sm.pivrow[c0 + j]), fs));
+      }
+      __syncthreads();
+      // X[:, c] = fs * X[:, c] + (Z - E_P) Xp[:, c] for the columns outside the panel
+      for (int q0 = 0; q0 < nother; q0 += BP) {
+        const int nc = min(BP, nother - q0);
+        for (int r0 = 0; r0 < n; r0 += BP) {
+          const int nr = min(BP, n - r0);
+          auto col = [&](int cc) {
+            const int x = q0 + cc;
+            return x < c0 ? x : x + bw;
+          };
+          auto fa = [&](int r, int j) -> cx<double> {
+            cx<double> z = ldg(X + (size_t)(c0 + j) * LD + r0 + r);
+            if (r0 + r == sm.pivrow[c0 + j]) z.re -= 1.0;
+            return z;
+          };
+          auto fb = [&](int j, int cc) -> cx<double> {
+            return ldg(Xp + (size_t)j * LD + col(cc));
+          };
+          auto epi = [&](int r, int cc, cx<double> v, bool ok) {
+            if (!ok) return;
+            cx<double>* p = X + (size_t)col(cc) * LD + r0 + r;
+            stg(p, cadd(cscale(ldg(p), fs), v));
+          };
+          gemm_mfma<BW, BP>(nr, nc, bw, fa, fb, epi);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // un-permute: g[i][j] = f * X[p_i][q_j]
+  for (int i = threadIdx.x; i < n; i += BW * 64) sm.pinv[sm.pivrow[i]] = i;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n * n; i += BW * 64) {
+    const int j = i / n, r = i - j * n;
+    stg(K + (size_t)j * LD + r, cscale(ldg(X + (size_t)sm.pinv[j] * LD + sm.pivrow[r]), f));
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) {
+  __shared__ LargeSmem sm;
+  constexpr size_t FULL = (size_t)LD * LD;
+  cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * (BP * BP);
+  cx<double>* K = slot;
+  cx<double>* G1b[2] = {slot + FULL, slot + 2 * FULL};
+  cx<double>* X = slot + 3 * FULL;
+  cx<double>* Y = slot + 4 * FULL;
+  cx<double>* Xp = slot + 5 * FULL;
+  const int H = 2 * a.L;
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const double t = a.t;
+
+  for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
+    const Tuple q = make_tuple_(a, tau);
+    if (threadIdx.x == 0) sm.flag = 0;
+    __syncthreads();
+    cx<double> A[BS][BC];
+    int cur = 0;
+    for (int h = 0; h < H; ++h) {
+      const int e = half_parity(h, a.parity);
+      const int n = half_size(a.N, e);
+      const double mx = block_max<BW>(build_M_large(a, q, h, K, X), sm.red);
+      invert_panels(n, pow2_scale(mx), X, Xp, K, A, sm);
+      if (h == 0) {
+        for (int i = threadIdx.x; i < n * n; i += BW * 64) {
+          const int c = i / n, r = i - c * n;
+          stg(G1b[0] + (size_t)c * LD + r, ldg(K + (size_t)c * LD + r));
+        }
+        __syncthreads();
+        continue;
+      }
+      // G1_h = (G1_{h-1} C_{h-1}) g_h in 128 x 128 output blocks (ping-pong)
+      const cx<double>* G1r = G1b[cur];
+      cx<double>* G1w = G1b[cur ^ 1];
+      const int nL = half_size(a.N, e ^ 1);
+      const bool rhalf = (h & 1) != 0;
+      for (int r0 = 0; r0 < n1; r0 += BP) {
+        for (int c0 = 0; c0 < n; c0 += BP) {
+          auto fa = [&](int r, int k) -> cx<double> {
+            if (!rhalf) return cscale(ldg(G1r + (size_t)k * LD + r0 + r), t);
+            const int k0 = nb_lo(k, e), k1 = nb_hi(k, e);
+            cx<double> acc = mk(0.0, 0.0);
+            if (k0 >= 0) acc = ldg(G1r + (size_t)k0 * LD + r0 + r);
+            if (k1 < nL) acc = cadd(acc, ldg(G1r + (size_t)k1 * LD + r0 + r));
+            return cscale(acc, t);
+          };
+          auto fb = [&](int k, int c) -> cx<double> {
+            return ldg(K + (size_t)k * LD + c0 + c);  // g[c0 + c][k] = g[k][c0 + c]
+          };
+          auto epi = [&](int r, int c, cx<double> v, bool ok) {
+            if (ok) stg(G1w + (size_t)(c0 + c) * LD + r0 + r, v);
+          };
+          gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, n - c0), n, fa, fb, epi);
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+
+    // T = sum_{p,q} d_p d_q |(Phi_L^T G1 Phi_R)_pq|^2
+    const cx<double>* G = G1b[cur];
+    const int nlast = half_size(a.N, half_parity(H - 1, a.parity));
+    const double* phiL = a.phi;
+    const double* phiR = a.phi + (size_t)a.P * LD;
+    for (int r0 = 0; r0 < n1; r0 += BP)
+      for (int c0 = 0; c0 < a.P; c0 += BP) {
+        auto fa = [&](int r, int k) -> cx<double> { return ldg(G + (size_t)k * LD + r0 + r); };
+        auto fb = [&](int k, int c) -> cx<double> {
+          return mk(phiR[(size_t)(c0 + c) * LD + k], 0.0);
+        };
+        auto epi = [&](int r, int c, cx<double> v, bool ok) {
+          if (ok) stg(Y + (size_t)(c0 + c) * LD + r0 + r, v);
+        };
+        gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, a.P - c0), nlast, fa, fb, epi);
+      }
+    __syncthreads();
+    double part = 0.0;
+    for (int r0 = 0; r0 < a.P; r0 += BP)
+      for (int c0 = 0; c0 < a.P; c0 += BP) {
+        auto fa = [&](int r, int k) -> cx<double> {
+          return mk(phiL[(size_t)(r0 + r) * LD + k], 0.0);
+        };
+        auto fb = [&](int k, int c) -> cx<double> { return ldg(Y + (size_t)(c0 + c) * LD + k); };
+        auto epi = [&](int r, int c, cx<double> v, bool ok) {
+          if (!ok) return;
+          const double dp = -2.0 * q.sig[r0 + r].im, dq = -2.0 * q.sig[c0 + c].im;
+          part += dp * dq * (v.re * v.re + v.im * v.im);
+        };
+        gemm_mfma<BW, BP>(min(BP, a.P - r0), min(BP, a.P - c0), n1, fa, fb, epi);
+      }
+    const double T = block_sum<BW>(part, sm.red);
+    if (threadIdx.x == 0) {
+      int st = a.lstat[q.e];
+      if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
+      if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
+      if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
+      a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
+      if (a.status) a.status[tau] = st;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+const void* large_kernel_ptr() { return (const void*)rgf_fwd_large_kernel; }
+
+TileCfg large_block_tile() { return TileCfg{-1, BW, BS, BC}; }
+
+int large_slot_blocks() { return kSlotBlocks; }
+
+hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
+                                double* T_out, int32_t* status_out, char* ws, hipStream_t s) {
+  if (p.ntuples == 0) return hipSuccess;
+  hipError_t err = launch_lead(p, E, ws, s);
+  if (err != hipSuccess) return err;
+  SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.N = p.N;
+  a.L = p.L;
+  a.parity = p.parity;
+  a.P = p.P;
+  a.t = p.t;
+  a.eta = p.eta;
+  a.E = E;
+  a.nE = p.nE;
+  a.eps = eps;
+  a.nreal = p.nreal;
+  a.sigma = reinterpret_cast<const cx<double>*>(ws + p.off_sigma);
+  a.phi = reinterpret_cast<const double*>(ws + p.off_phi);
+  a.lstat = reinterpret_cast<const int32_t*>(ws + p.off_lstat);
+  a.T_out = T_out;
+  a.status = status_out;
+  a.slots = reinterpret_cast<cx<double>*>(ws + p.off_slots);
+  a.slot_mats = p.slot_mats;
+  a.ntuples = p.ntuples;
+  hipLaunchKernelGGL(rgf_fwd_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rgf

@@ -196,7 +196,7 @@ hipError_t launch_lead(const Plan& p, const double* E, char* ws, hipStream_t s) 
   auto* sigma = reinterpret_cast<cx<double>*>(ws + p.off_sigma);
   auto* phi = reinterpret_cast<double*>(ws + p.off_phi);
   auto* lstat = reinterpret_cast<int32_t*>(ws + p.off_lstat);
-  int ld = p.tile.NP();
+  const int ld = p.phi_ld;
   if (p.nE > 0) {
     hipLaunchKernelGGL(lead_modes_kernel, dim3((unsigned)p.nE), dim3(128), 0, s, p.N,
                        p.P, p.t, p.eta, E, sigma, lstat);
@@ -218,7 +218,7 @@ hipError_t launch_export_sigma(const Plan& p, const double* E, double* sl, doubl
   int64_t total = p.nE * ((int64_t)nl * nl + (int64_t)nr * nr);
   if (total > 0) {
     hipLaunchKernelGGL(export_sigma_kernel, dim3((unsigned)((total + 255) / 256)),
-                       dim3(256), 0, s, p.P, p.tile.NP(), nl, nr, p.nE,
+                       dim3(256), 0, s, p.P, p.phi_ld, nl, nr, p.nE,
                        reinterpret_cast<const cx<double>*>(ws + p.off_sigma),
                        reinterpret_cast<const double*>(ws + p.off_phi), sl, sr);
     err = hipGetLastError();

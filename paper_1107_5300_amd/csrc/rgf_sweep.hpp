@@ -70,6 +70,13 @@ struct SweepSmem {
   int flag;
 };
 
+// Eq. (2) for unitary scattering bounds T by the number of open channels,
+// at most the P lead modes; a value outside [0, P] (beyond rounding) means
+// the recursion lost its accuracy and the tuple is flagged.
+__device__ __forceinline__ bool t_in_range(double T, int P) {
+  return T >= -1e-6 && T <= (double)P + 1e-6;
+}
+
 // Per-tuple constants.
 struct Tuple {
   int64_t r, e, idx;

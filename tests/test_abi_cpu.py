@@ -36,13 +36,13 @@ def test_version_and_strings():
     lib = L.lib()
     a, b = ctypes.c_int(), ctypes.c_int()
     assert lib.rgf_version(ctypes.byref(a), ctypes.byref(b)) == 0
-    assert (a.value, b.value) == (1, 0)
+    assert (a.value, b.value) == (1, 1)
     assert lib.rgf_status_string(-1) == b"RGF_ERR_INVALID_ARG"
     assert lib.rgf_status_string(-3) == b"RGF_ERR_WORKSPACE"
 
 
 @pytest.mark.parametrize("field,value,code", [
-    ("width_n", 1, -1), ("width_n", 100000, -4), ("width_n", 480, -4), ("width_n", 257, -4),
+    ("width_n", 1, -1), ("width_n", 100000, -4), ("width_n", 513, -4),
     ("length_l", 0, -1), ("parity", 2, -1),
     ("hopping_ev", 0.0, -1), ("hopping_ev", float("nan"), -1), ("eta_ev", 0.0, -1),
     ("eta_ev", -1e-8, -1), ("eta_ev", float("inf"), -1), ("struct_size", 8, -1),
@@ -124,18 +124,62 @@ def test_forward_kernels_use_no_scratch():
 
 
 def test_widest_supported_and_first_unsupported_width():
-    """n = ceil(N/2) must fit the register tiling (n <= 128): N = 256 plans,
-    N = 257 and the N = 480 workload report RGF_ERR_UNSUPPORTED for every
-    sweep entry point, before anything is enqueued."""
+    """N = 512 is the widest ribbon (two blocks of at most 128 rows per
+    half-slice); N = 513 reports RGF_ERR_UNSUPPORTED before anything is
+    enqueued."""
     from paper_1107_5300_amd import _lib as L
     lib = L.lib()
-    ok = L.make_desc(256, 4)
-    assert lib.rgf_workspace_bytes(ctypes.byref(ok), 4, 1, 0, 0, 0) > 0
-    assert lib.rgf_workspace_bytes(ctypes.byref(ok), 4, 1, 0, 1, 0) > 0
-    for N in (257, 480):
-        d = L.make_desc(N, 4)
-        assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 0, 0) == 0
-        rc = lib.rgf_ldos(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
-                          ctypes.c_void_p(16), None, 0, None, None, 0, None)
-        assert rc == L.RGF_ERR_UNSUPPORTED
-        assert b"outside [2, 256]" in lib.rgf_last_error_message()
+    for N in (256, 257, 480, 512):
+        ok = L.make_desc(N, 4)
+        assert lib.rgf_workspace_bytes(ctypes.byref(ok), 4, 1, 0, 0, 0) > 0, N
+    d = L.make_desc(513, 4)
+    assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 0, 0) == 0
+    rc = lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+                             ctypes.c_void_p(16), None, ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == L.RGF_ERR_UNSUPPORTED
+    assert b"outside [2, 512]" in lib.rgf_last_error_message()
+
+
+@pytest.mark.parametrize("N", [257, 480, 512])
+def test_wide_ribbons_fp64_conductance_only(N):
+    """Half-slices above 128 rows are inverted by blocks in FP64; the reverse
+    sweeps (rgf_grad, rgf_ldos) and the FP32 modes report
+    RGF_ERR_UNSUPPORTED for them before anything is enqueued, while N = 256
+    supports every entry point and precision."""
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    d = L.make_desc(N, 4)
+    for prec in (1, 2):
+        assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, prec, 0, 0) == 0
+        assert b"FP64 only" in lib.rgf_last_error_message()
+    assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 1, 0) == 0
+    assert b"reverse sweeps" in lib.rgf_last_error_message()
+    rc = lib.rgf_ldos(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+                      ctypes.c_void_p(16), None, 0, None, None, 0, None)
+    assert rc == L.RGF_ERR_UNSUPPORTED
+    rc = lib.rgf_grad(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+                      ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 0, None,
+                      None, 0, None)
+    assert rc == L.RGF_ERR_UNSUPPORTED
+    rc = lib.rgf_conductance(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 1,
+                             ctypes.c_void_p(16), None, ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == L.RGF_ERR_UNSUPPORTED
+    narrow = L.make_desc(256, 4)
+    for prec in (0, 1, 2):
+        for grad in (0, 1):
+            assert lib.rgf_workspace_bytes(ctypes.byref(narrow), 4, 1, prec, grad, 0) > 0
+
+
+def test_wide_ribbon_workspace_scales_with_grid():
+    """The blocked path's workspace: lead tables with leading dimension 256
+    plus 21 blocks of 128 x 128 complex128 per persistent slot (five 256 x 256
+    matrices and the staged pivot rows; the grid is at most the tuple
+    count)."""
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    d = L.make_desc(480, 4)
+    one = lib.rgf_workspace_bytes(ctypes.byref(d), 1, 1, 0, 0, 0)
+    two = lib.rgf_workspace_bytes(ctypes.byref(d), 2, 1, 0, 0, 0)
+    slot = 21 * 128 * 128 * 16
+    assert one >= slot + 2 * 240 * 256 * 8
+    assert two - one >= slot

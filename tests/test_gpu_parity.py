@@ -159,6 +159,23 @@ def test_invariants_at_scale(P):
     assert np.abs(a - b).max() <= 1e-9
 
 
+@pytest.mark.parametrize("N", [30, 60, 120])
+def test_zero_energy_pristine_flagged_or_exact(P, N):
+    """E = 0 exactly with zero on-site energies: every half-slice is one
+    sublattice with no diagonal term, so its left-connected Green's function
+    grows like 1/eta and the half-slice recursion loses its accuracy. The
+    tuple must come out flagged (RGF_TUPLE_OUT_OF_RANGE, T = NaN) or equal to
+    the oracle (which works on whole slices)."""
+    _say("zero energy pristine", N)
+    T, st = _gpu_T(P, N, 5, 0, W.T_HOP, [0.0, 0.2 * abs(W.T_HOP)], None, status=True)
+    assert st[0, 1] == 0
+    want = O.transmission(N, 5, W.T_HOP, W.ETA, 0.0, None, 0)
+    if st[0, 0] != 0:
+        assert st[0, 0] == 4 and np.isnan(T[0, 0])
+    else:
+        assert abs(T[0, 0] - want) <= TOL_SMALL * max(1.0, abs(want)), (T[0, 0], want)
+
+
 def test_nan_energy_sets_status(P):
     _say("nan energy")
     T, st = _gpu_T(P, 10, 5, 0, W.T_HOP, [0.3, float("nan")], None, status=True)
