@@ -255,6 +255,7 @@ hipError_t launch_grad(const Plan& p, const double* E, const double* eps, const 
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
+  if (p.large) return launch_grad_large(p, E, eps, dL_dT, T_out, dL_deps, status_out, ws, s);
   if (p.ntuples == 0) return hipSuccess;
   hipError_t err = launch_lead(p, E, ws, s);
   if (err != hipSuccess) return err;

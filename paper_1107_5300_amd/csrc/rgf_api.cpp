@@ -97,11 +97,6 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
       return fail(RGF_ERR_UNSUPPORTED,
                   "width_n = %d: half-slices above %d rows run in FP64 only", q.N,
                   kTileMaxRows);
-    if (q.want_grad)
-      return fail(RGF_ERR_UNSUPPORTED,
-                  "width_n = %d: the reverse sweeps support half-slices of at most %d rows "
-                  "(width_n <= %d)",
-                  q.N, kTileMaxRows, 2 * kTileMaxRows);
     q.tile = large_block_tile();
   } else if (!pick_tile(q.nmax, precision, &q.tile)) {
     return fail(RGF_ERR_UNSUPPORTED, "width_n = %d exceeds the register tiling", q.N);
@@ -121,9 +116,10 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   }
   const int NP = q.tile.NP();
   if (q.large) {
-    q.grid = persistent_grid_large(std::max<int64_t>(q.ntuples, 1));
+    q.grid = persistent_grid_large(std::max<int64_t>(q.ntuples, 1), q.want_grad);
     q.slot_elems = (int64_t)kTileMaxRows * kTileMaxRows;
-    q.slot_mats = large_slot_blocks();
+    q.slot_mats = large_slot_blocks(q.want_grad);
+    q.mat_elems = (int64_t)kLargeLd * kLargeLd;
     q.phi_ld = kLargeLd;
   } else {
     int tid = 0, per_cu = 0;
@@ -132,6 +128,7 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
                              q.per_cu);
     q.slot_elems = (int64_t)NP * NP;
     q.slot_mats = slot_matrices(precision, q.want_grad);
+    q.mat_elems = q.slot_elems;
     q.phi_ld = NP;
   }
   size_t off = 0;
@@ -156,9 +153,9 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
     q.ckpt_stride = stride;
     q.n_ckpt = (H + stride - 1) / stride;
     q.off_ckpt = off;
-    off = align_up(off + (size_t)q.grid * q.n_ckpt * 2 * q.slot_elems * 16, 256);
+    off = align_up(off + (size_t)q.grid * q.n_ckpt * 2 * q.mat_elems * 16, 256);
     q.off_seg = off;
-    off = align_up(off + (size_t)q.grid * stride * 2 * q.slot_elems * 16, 256);
+    off = align_up(off + (size_t)q.grid * stride * 2 * q.mat_elems * 16, 256);
   }
   q.total = off;
   *p = q;
@@ -215,13 +212,13 @@ int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad,
   return (int)g;
 }
 
-int persistent_grid_large(int64_t ntuples) {
+int persistent_grid_large(int64_t ntuples, bool grad) {
   int dev = 0, ncu = 256, occ = 1;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     int o = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, large_kernel_ptr(),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, large_kernel_ptr(grad),
                                                      large_block_tile().threads(), 0) ==
             hipSuccess &&
         o > 0)
@@ -311,6 +308,11 @@ int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_e
   Plan p;
   int st = make_plan(desc, n_energies, n_real, precision, 1, ckpt_stride, &p);
   if (st != RGF_OK) return st;
+  if (p.large)
+    return fail(RGF_ERR_UNSUPPORTED,
+                "width_n = %d: the local density of states supports half-slices of at most "
+                "%d rows (width_n <= %d)",
+                p.N, kTileMaxRows, 2 * kTileMaxRows);
   if (n_energies > 0) {
     if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
     if (!ldos_out) return fail(RGF_ERR_INVALID_ARG, "ldos_out is NULL");

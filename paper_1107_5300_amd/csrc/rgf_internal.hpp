@@ -52,6 +52,7 @@ struct Plan {
   int grid;           // persistent workgroups
   int per_cu;         // forced slots per CU (0 = occupancy limit)
   int64_t slot_elems; // complex elements of one matrix buffer (NP*NP)
+  int64_t mat_elems;  // complex elements of one stored restart matrix
   int slot_mats;      // matrix buffers per slot
   // byte offsets
   size_t off_sigma, off_phi, off_lstat, off_status, off_slots, off_ckpt, off_seg,
@@ -83,8 +84,8 @@ hipError_t launch_grad(const Plan& p, const double* E, const double* eps,
 // Persistent grid size for a tile config on the current device.
 int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad,
                     int per_cu = 0);
-// The same for the blocked wide-half-slice kernel.
-int persistent_grid_large(int64_t ntuples);
+// The same for the blocked wide-half-slice kernels.
+int persistent_grid_large(int64_t ntuples, bool grad);
 
 // Kernel entry of the forward sweep / adjoint for a tile and precision.
 const void* fwd_kernel_ptr(const TileCfg& t, int precision);
@@ -95,14 +96,17 @@ const void* grad_kernel_ptr(const TileCfg& t, int precision);
 // Matrix buffers (NP x NP complex128) per persistent slot.
 int slot_matrices(int precision, bool grad);
 
-// Blocked forward sweep for kTileMaxRows < n <= kLargeLd (FP64).
+// Blocked forward sweep and gradient for kTileMaxRows < n <= kLargeLd (FP64).
 hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
                                 double* T_out, int32_t* status_out, char* ws, hipStream_t s);
-const void* large_kernel_ptr();
-// Register tiling of the blocked kernel's elimination panels (id -1: not a
-// table entry), and its buffers per slot in units of kTileMaxRows^2
+hipError_t launch_grad_large(const Plan& p, const double* E, const double* eps,
+                             const double* dL_dT, double* T_out, double* dL_deps,
+                             int32_t* status_out, char* ws, hipStream_t s);
+const void* large_kernel_ptr(bool grad);
+// Register tiling of the blocked kernels' elimination panels (id -1: not a
+// table entry), and their buffers per slot in units of kTileMaxRows^2
 // complex128.
 TileCfg large_block_tile();
-int large_slot_blocks();
+int large_slot_blocks(bool grad);
 
 }  // namespace rgf

@@ -28,8 +28,10 @@
 //
 // Workspace per persistent workgroup, complex128, leading dimension LD = 256
 // (column-major): K (g_h), G1 ping-pong x 2, X (the matrix being inverted),
-// Y (trace scratch), and Xp (the staged pivot rows, b x LD row-major).
-// g_h is complex symmetric, so it is read in whichever order is contiguous.
+// Y (trace scratch), and Xp (the staged pivot rows, b x LD row-major); the
+// gradient kernel adds a second K, S, and Z, Q ping-pong pairs, plus the
+// restart states and the segment buffer. g_h is complex symmetric, so it is
+// read in whichever order is contiguous.
 
 #include <string.h>
 
@@ -44,7 +46,9 @@ constexpr int BW = 8, BS = 4, BC = 8;      // panel register tile: 256 rows x 64
 constexpr int NR = 64 * BS, PB = BW * BC;  // rows held, panel width
 constexpr int BP = kTileMaxRows;           // output block of the GEMM calls
 static_assert(NR == LD && 2 * BP == LD, "panel height and GEMM blocks");
+constexpr size_t FULL = (size_t)LD * LD;   // complex elements of one full matrix
 constexpr int kSlotBlocks = 5 * 4 + 1;     // K, G1 x 2, X, Y (4 blocks each); Xp
+constexpr int kGradSlotBlocks = 11 * 4 + 1;  // K x 2, G1 x 2, X, Y, S, Z x 2, Q x 2; Xp
 static_assert(PB * LD <= BP * BP, "the staged pivot rows fit one block");
 
 struct LargeSmem {
@@ -52,6 +56,7 @@ struct LargeSmem {
   int pivrow[NR];                   // pivot row of each elimination step
   int pinv[NR];
   double red[2 * BW];
+  double rowacc[NR];                // gradient row sums of the reverse sweep
   int flag;
 };
 
@@ -297,103 +302,124 @@ __device__ __forceinline__ void invert_panels(int n, double f, cx<double>* X, cx
   __syncthreads();
 }
 
+// One half-slice step: g_h from g_{h-1} (Kprev) into Kout and G1_h from
+// G1_{h-1} (G1prev) into G1out (G1 buffers must differ, K may be the same
+// buffer; at h = 0 neither input is read). X and Xp are the inversion's
+// scratch.
+__device__ __forceinline__ void large_step(const SweepArgs& a, const Tuple& q, int h,
+                                           const cx<double>* Kprev, cx<double>* Kout,
+                                           const cx<double>* G1prev, cx<double>* G1out,
+                                           cx<double>* X, cx<double>* Xp,
+                                           cx<double> (&A)[BS][BC], LargeSmem& sm) {
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const double mx = block_max<BW>(build_M_large(a, q, h, Kprev, X), sm.red);
+  invert_panels(n, pow2_scale(mx), X, Xp, Kout, A, sm);
+  if (h == 0) {
+    for (int i = threadIdx.x; i < n * n; i += BW * 64) {
+      const int c = i / n, r = i - c * n;
+      stg(G1out + (size_t)c * LD + r, ldg(Kout + (size_t)c * LD + r));
+    }
+    __syncthreads();
+    return;
+  }
+  // G1_h = (G1_{h-1} C_{h-1}) g_h in 128 x 128 output blocks
+  const int nL = half_size(a.N, e ^ 1);
+  const bool rhalf = (h & 1) != 0;
+  const double t = a.t;
+  for (int r0 = 0; r0 < n1; r0 += BP) {
+    for (int c0 = 0; c0 < n; c0 += BP) {
+      auto fa = [&](int r, int k) -> cx<double> {
+        if (!rhalf) return cscale(ldg(G1prev + (size_t)k * LD + r0 + r), t);
+        const int k0 = nb_lo(k, e), k1 = nb_hi(k, e);
+        cx<double> acc = mk(0.0, 0.0);
+        if (k0 >= 0) acc = ldg(G1prev + (size_t)k0 * LD + r0 + r);
+        if (k1 < nL) acc = cadd(acc, ldg(G1prev + (size_t)k1 * LD + r0 + r));
+        return cscale(acc, t);
+      };
+      auto fb = [&](int k, int c) -> cx<double> {
+        return ldg(Kout + (size_t)k * LD + c0 + c);  // g[c0 + c][k] = g[k][c0 + c]
+      };
+      auto epi = [&](int r, int c, cx<double> v, bool ok) {
+        if (ok) stg(G1out + (size_t)(c0 + c) * LD + r0 + r, v);
+      };
+      gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, n - c0), n, fa, fb, epi);
+    }
+  }
+  __syncthreads();
+}
+
+// T = sum_{p,q} d_p d_q |S_pq|^2 with S = Phi_L^T G Phi_R (G = G_{1L}, n1 x
+// nlast), through Y = G Phi_R; S is also stored (column-major) when Sout is
+// non-null. Every thread returns T.
+__device__ __forceinline__ double large_trace(const SweepArgs& a, const Tuple& q,
+                                              const cx<double>* G, cx<double>* Y,
+                                              cx<double>* Sout, LargeSmem& sm) {
+  const int H = 2 * a.L;
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const int nlast = half_size(a.N, half_parity(H - 1, a.parity));
+  const double* phiL = a.phi;
+  const double* phiR = a.phi + (size_t)a.P * LD;
+  for (int r0 = 0; r0 < n1; r0 += BP)
+    for (int c0 = 0; c0 < a.P; c0 += BP) {
+      auto fa = [&](int r, int k) -> cx<double> { return ldg(G + (size_t)k * LD + r0 + r); };
+      auto fb = [&](int k, int c) -> cx<double> {
+        return mk(phiR[(size_t)(c0 + c) * LD + k], 0.0);
+      };
+      auto epi = [&](int r, int c, cx<double> v, bool ok) {
+        if (ok) stg(Y + (size_t)(c0 + c) * LD + r0 + r, v);
+      };
+      gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, a.P - c0), nlast, fa, fb, epi);
+    }
+  __syncthreads();
+  double part = 0.0;
+  for (int r0 = 0; r0 < a.P; r0 += BP)
+    for (int c0 = 0; c0 < a.P; c0 += BP) {
+      auto fa = [&](int r, int k) -> cx<double> {
+        return mk(phiL[(size_t)(r0 + r) * LD + k], 0.0);
+      };
+      auto fb = [&](int k, int c) -> cx<double> { return ldg(Y + (size_t)(c0 + c) * LD + k); };
+      auto epi = [&](int r, int c, cx<double> v, bool ok) {
+        if (!ok) return;
+        const double dp = -2.0 * q.sig[r0 + r].im, dq = -2.0 * q.sig[c0 + c].im;
+        part += dp * dq * (v.re * v.re + v.im * v.im);
+        if (Sout) stg(Sout + (size_t)(c0 + c) * LD + r0 + r, v);
+      };
+      gemm_mfma<BW, BP>(min(BP, a.P - r0), min(BP, a.P - c0), n1, fa, fb, epi);
+    }
+  return block_sum<BW>(part, sm.red);
+}
+
+__device__ __forceinline__ int tuple_status(const SweepArgs& a, const Tuple& q, double T,
+                                            const LargeSmem& sm) {
+  int st = a.lstat[q.e];
+  if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
+  if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
+  if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
+  return st;
+}
+
 __global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) {
   __shared__ LargeSmem sm;
-  constexpr size_t FULL = (size_t)LD * LD;
   cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * (BP * BP);
-  cx<double>* K = slot;
+  cx<double>* K = slot;  // g_h in place: M_h is built from it before it is rewritten
   cx<double>* G1b[2] = {slot + FULL, slot + 2 * FULL};
   cx<double>* X = slot + 3 * FULL;
   cx<double>* Y = slot + 4 * FULL;
   cx<double>* Xp = slot + 5 * FULL;
   const int H = 2 * a.L;
-  const int n1 = half_size(a.N, half_parity(0, a.parity));
-  const double t = a.t;
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
     if (threadIdx.x == 0) sm.flag = 0;
     __syncthreads();
     cx<double> A[BS][BC];
-    int cur = 0;
-    for (int h = 0; h < H; ++h) {
-      const int e = half_parity(h, a.parity);
-      const int n = half_size(a.N, e);
-      const double mx = block_max<BW>(build_M_large(a, q, h, K, X), sm.red);
-      invert_panels(n, pow2_scale(mx), X, Xp, K, A, sm);
-      if (h == 0) {
-        for (int i = threadIdx.x; i < n * n; i += BW * 64) {
-          const int c = i / n, r = i - c * n;
-          stg(G1b[0] + (size_t)c * LD + r, ldg(K + (size_t)c * LD + r));
-        }
-        __syncthreads();
-        continue;
-      }
-      // G1_h = (G1_{h-1} C_{h-1}) g_h in 128 x 128 output blocks (ping-pong)
-      const cx<double>* G1r = G1b[cur];
-      cx<double>* G1w = G1b[cur ^ 1];
-      const int nL = half_size(a.N, e ^ 1);
-      const bool rhalf = (h & 1) != 0;
-      for (int r0 = 0; r0 < n1; r0 += BP) {
-        for (int c0 = 0; c0 < n; c0 += BP) {
-          auto fa = [&](int r, int k) -> cx<double> {
-            if (!rhalf) return cscale(ldg(G1r + (size_t)k * LD + r0 + r), t);
-            const int k0 = nb_lo(k, e), k1 = nb_hi(k, e);
-            cx<double> acc = mk(0.0, 0.0);
-            if (k0 >= 0) acc = ldg(G1r + (size_t)k0 * LD + r0 + r);
-            if (k1 < nL) acc = cadd(acc, ldg(G1r + (size_t)k1 * LD + r0 + r));
-            return cscale(acc, t);
-          };
-          auto fb = [&](int k, int c) -> cx<double> {
-            return ldg(K + (size_t)k * LD + c0 + c);  // g[c0 + c][k] = g[k][c0 + c]
-          };
-          auto epi = [&](int r, int c, cx<double> v, bool ok) {
-            if (ok) stg(G1w + (size_t)(c0 + c) * LD + r0 + r, v);
-          };
-          gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, n - c0), n, fa, fb, epi);
-        }
-      }
-      __syncthreads();
-      cur ^= 1;
-    }
-
-    // T = sum_{p,q} d_p d_q |(Phi_L^T G1 Phi_R)_pq|^2
-    const cx<double>* G = G1b[cur];
-    const int nlast = half_size(a.N, half_parity(H - 1, a.parity));
-    const double* phiL = a.phi;
-    const double* phiR = a.phi + (size_t)a.P * LD;
-    for (int r0 = 0; r0 < n1; r0 += BP)
-      for (int c0 = 0; c0 < a.P; c0 += BP) {
-        auto fa = [&](int r, int k) -> cx<double> { return ldg(G + (size_t)k * LD + r0 + r); };
-        auto fb = [&](int k, int c) -> cx<double> {
-          return mk(phiR[(size_t)(c0 + c) * LD + k], 0.0);
-        };
-        auto epi = [&](int r, int c, cx<double> v, bool ok) {
-          if (ok) stg(Y + (size_t)(c0 + c) * LD + r0 + r, v);
-        };
-        gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, a.P - c0), nlast, fa, fb, epi);
-      }
-    __syncthreads();
-    double part = 0.0;
-    for (int r0 = 0; r0 < a.P; r0 += BP)
-      for (int c0 = 0; c0 < a.P; c0 += BP) {
-        auto fa = [&](int r, int k) -> cx<double> {
-          return mk(phiL[(size_t)(r0 + r) * LD + k], 0.0);
-        };
-        auto fb = [&](int k, int c) -> cx<double> { return ldg(Y + (size_t)(c0 + c) * LD + k); };
-        auto epi = [&](int r, int c, cx<double> v, bool ok) {
-          if (!ok) return;
-          const double dp = -2.0 * q.sig[r0 + r].im, dq = -2.0 * q.sig[c0 + c].im;
-          part += dp * dq * (v.re * v.re + v.im * v.im);
-        };
-        gemm_mfma<BW, BP>(min(BP, a.P - r0), min(BP, a.P - c0), n1, fa, fb, epi);
-      }
-    const double T = block_sum<BW>(part, sm.red);
+    for (int h = 0; h < H; ++h)
+      large_step(a, q, h, K, K, G1b[(h + 1) & 1], G1b[h & 1], X, Xp, A, sm);
+    const double T = large_trace(a, q, G1b[(H - 1) & 1], Y, nullptr, sm);
     if (threadIdx.x == 0) {
-      int st = a.lstat[q.e];
-      if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
-      if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
-      if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
+      const int st = tuple_status(a, q, T, sm);
       a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
       if (a.status) a.status[tau] = st;
     }
@@ -401,19 +427,219 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) 
   }
 }
 
+// Gradient of T with respect to every on-site energy: the reverse sweep of
+// rgf_adjoint.hip (Dyson's equation, Eq. (3), cut between half-slices),
+//   Z_h = g_h (C_h Z_{h+1}),  Q_h = G1_h^T + g_h (C_h Q_{h+1}),
+//   dT/d eps_{h,a} = 2 Re sum_c Z_h[a][c] Q_h[a][c],
+// with Z_last = g_last Phi_R (D S^dagger D) Phi_L^T, on workspace-resident
+// matrices (Z and Q row-major, ping-pong: the blocked products read all of
+// Z_{h+1} while writing Z_h). Restart states (g_h, G1_h) are stored every
+// `stride` half-slices and each segment is recomputed before it is walked
+// back.
+__global__ __launch_bounds__(BW * 64, 2) void rgf_grad_large_kernel(SweepArgs a) {
+  __shared__ LargeSmem sm;
+  cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * (BP * BP);
+  cx<double>* Kb[2] = {slot, slot + FULL};
+  cx<double>* G1b[2] = {slot + 2 * FULL, slot + 3 * FULL};
+  cx<double>* X = slot + 4 * FULL;
+  cx<double>* Y = slot + 5 * FULL;
+  cx<double>* Sb = slot + 6 * FULL;
+  cx<double>* Zb[2] = {slot + 7 * FULL, slot + 8 * FULL};
+  cx<double>* Qb[2] = {slot + 9 * FULL, slot + 10 * FULL};
+  cx<double>* Xp = slot + 11 * FULL;
+  cx<double>* ck = a.ckpt + (size_t)blockIdx.x * a.n_ckpt * 2 * FULL;
+  cx<double>* sg = a.seg + (size_t)blockIdx.x * a.stride * 2 * FULL;
+  const int H = 2 * a.L;
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const int nlast = half_size(a.N, half_parity(H - 1, a.parity));
+  const double* phiL = a.phi;
+  const double* phiR = a.phi + (size_t)a.P * LD;
+
+  for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
+    const Tuple q = make_tuple_(a, tau);
+    if (threadIdx.x == 0) sm.flag = 0;
+    __syncthreads();
+    cx<double> A[BS][BC];
+
+    // ---- forward sweep, restart states after every stride half-slices
+    for (int h = 0; h < H; ++h) {
+      large_step(a, q, h, Kb[(h + 1) & 1], Kb[h & 1], G1b[(h + 1) & 1], G1b[h & 1], X, Xp, A,
+                 sm);
+      if ((h + 1) % a.stride == 0 && h + 1 < H) {
+        cx<double>* c = ck + (size_t)((h + 1) / a.stride) * 2 * FULL;
+        for (size_t i = threadIdx.x; i < FULL; i += BW * 64) {
+          stg(c + i, ldg(Kb[h & 1] + i));
+          stg(c + FULL + i, ldg(G1b[h & 1] + i));
+        }
+        __syncthreads();
+      }
+    }
+    const cx<double>* Klast = Kb[(H - 1) & 1];
+    const double T = large_trace(a, q, G1b[(H - 1) & 1], Y, Sb, sm);
+    const int st = tuple_status(a, q, T, sm);
+    if (threadIdx.x == 0) {
+      a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
+      if (a.status) a.status[tau] = st;
+    }
+    const double wt = a.dL_dT[tau];
+    if (st != RGF_TUPLE_OK || wt == 0.0) {
+      __syncthreads();
+      continue;
+    }
+
+    // ---- Z_last = g_last Phi_R R Phi_L^T with R = D S^dagger D (R[k][p] =
+    // d_k conj(S[p][k]) d_p): V = g_last Phi_R -> Y, V2 = V R -> X,
+    // Z_last = V2 Phi_L^T -> Z (row-major)
+    for (int r0 = 0; r0 < nlast; r0 += BP)
+      for (int c0 = 0; c0 < a.P; c0 += BP) {
+        auto fa = [&](int r, int k) -> cx<double> {
+          return ldg(Klast + (size_t)k * LD + r0 + r);
+        };
+        auto fb = [&](int k, int c) -> cx<double> {
+          return mk(phiR[(size_t)(c0 + c) * LD + k], 0.0);
+        };
+        auto epi = [&](int r, int c, cx<double> v, bool ok) {
+          if (ok) stg(Y + (size_t)(c0 + c) * LD + r0 + r, v);
+        };
+        gemm_mfma<BW, BP>(min(BP, nlast - r0), min(BP, a.P - c0), nlast, fa, fb, epi);
+      }
+    __syncthreads();
+    for (int r0 = 0; r0 < nlast; r0 += BP)
+      for (int c0 = 0; c0 < a.P; c0 += BP) {
+        auto fa = [&](int r, int k) -> cx<double> { return ldg(Y + (size_t)k * LD + r0 + r); };
+        auto fb = [&](int k, int c) -> cx<double> {
+          const cx<double> sv = ldg(Sb + (size_t)k * LD + c0 + c);  // S[c0 + c][k]
+          const double f = 4.0 * q.sig[k].im * q.sig[c0 + c].im;    // d_k d_p
+          return mk(f * sv.re, -f * sv.im);
+        };
+        auto epi = [&](int r, int c, cx<double> v, bool ok) {
+          if (ok) stg(X + (size_t)(c0 + c) * LD + r0 + r, v);
+        };
+        gemm_mfma<BW, BP>(min(BP, nlast - r0), min(BP, a.P - c0), a.P, fa, fb, epi);
+      }
+    __syncthreads();
+    int cz = 0;
+    for (int r0 = 0; r0 < nlast; r0 += BP)
+      for (int c0 = 0; c0 < n1; c0 += BP) {
+        auto fa = [&](int r, int k) -> cx<double> { return ldg(X + (size_t)k * LD + r0 + r); };
+        auto fb = [&](int k, int c) -> cx<double> {
+          return mk(phiL[(size_t)k * LD + c0 + c], 0.0);
+        };
+        auto epi = [&](int r, int c, cx<double> v, bool ok) {
+          if (ok) stg(Zb[0] + (size_t)(r0 + r) * LD + c0 + c, v);
+        };
+        gemm_mfma<BW, BP>(min(BP, nlast - r0), min(BP, n1 - c0), a.P, fa, fb, epi);
+      }
+    __syncthreads();
+
+    // ---- backward over segments
+    const int nseg = (H + a.stride - 1) / a.stride;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int h0 = sgi * a.stride;
+      const int h1 = min(H, h0 + a.stride);
+      for (int h = h0; h < h1; ++h) {
+        const int j = h - h0;
+        const cx<double>* Kp = (j == 0) ? ck + (size_t)sgi * 2 * FULL : sg + (size_t)(j - 1) * 2 * FULL;
+        cx<double>* Ko = sg + (size_t)j * 2 * FULL;
+        large_step(a, q, h, Kp, Ko, Kp + FULL, Ko + FULL, X, Xp, A, sm);
+      }
+      for (int h = h1 - 1; h >= h0; --h) {
+        const cx<double>* gh = sg + (size_t)(h - h0) * 2 * FULL;
+        const cx<double>* G1h = gh + FULL;
+        const int e = half_parity(h, a.parity);
+        const int n = half_size(a.N, e);
+        for (int i = threadIdx.x; i < NR; i += BW * 64) sm.rowacc[i] = 0.0;
+        __syncthreads();
+        if (h < H - 1) {
+          const int en = half_parity(h + 1, a.parity);
+          const int nn = half_size(a.N, en);
+          const double t = a.t;
+          const cx<double>* Zo = Zb[cz];
+          cx<double>* Zn = Zb[cz ^ 1];
+          const cx<double>* Qo = Qb[cz];
+          cx<double>* Qn = Qb[cz ^ 1];
+          // (C_h X)[k][c]: h even (L_i -> R_i): t (X[k + 1 - eR][c] + X[k - eR][c]);
+          //                h odd  (R_i -> L_{i+1}): t X[k][c]
+          auto capply = [&](const cx<double>* Xm, int k, int c) -> cx<double> {
+            if (h & 1) return cscale(ldg(Xm + (size_t)k * LD + c), t);
+            const int b0 = k + 1 - en, b1 = k - en;
+            cx<double> acc = mk(0.0, 0.0);
+            if (b0 >= 0 && b0 < nn) acc = ldg(Xm + (size_t)b0 * LD + c);
+            if (b1 >= 0 && b1 < nn) acc = cadd(acc, ldg(Xm + (size_t)b1 * LD + c));
+            return cscale(acc, t);
+          };
+          for (int r0 = 0; r0 < n; r0 += BP)
+            for (int c0 = 0; c0 < n1; c0 += BP) {
+              auto fa = [&](int r, int k) -> cx<double> {
+                return ldg(gh + (size_t)k * LD + r0 + r);
+              };
+              auto fb = [&](int k, int c) -> cx<double> { return capply(Zo, k, c0 + c); };
+              auto epi = [&](int r, int c, cx<double> v, bool ok) {
+                if (ok) stg(Zn + (size_t)(r0 + r) * LD + c0 + c, v);
+              };
+              gemm_mfma<BW, BP>(min(BP, n - r0), min(BP, n1 - c0), n, fa, fb, epi);
+            }
+          __syncthreads();
+          for (int r0 = 0; r0 < n; r0 += BP)
+            for (int c0 = 0; c0 < n1; c0 += BP) {
+              auto fa = [&](int r, int k) -> cx<double> {
+                return ldg(gh + (size_t)k * LD + r0 + r);
+              };
+              auto fb = [&](int k, int c) -> cx<double> { return capply(Qo, k, c0 + c); };
+              auto epi = [&](int r, int c, cx<double> v, bool ok) {
+                double part = 0.0;
+                if (ok) {
+                  const size_t o = (size_t)(r0 + r) * LD + c0 + c;
+                  v = cadd(v, ldg(G1h + o));  // G1_h^T[r][c] = G1_h[c][r]
+                  const cx<double> z = ldg(Zn + o);
+                  part = z.re * v.re - z.im * v.im;
+                  stg(Qn + o, v);
+                }
+                part += __shfl_xor(part, 1);
+                part += __shfl_xor(part, 2);
+                part += __shfl_xor(part, 4);
+                part += __shfl_xor(part, 8);
+                if ((lane_id() & 15) == 0 && r0 + r < n) atomicAdd(&sm.rowacc[r0 + r], part);
+              };
+              gemm_mfma<BW, BP>(min(BP, n - r0), min(BP, n1 - c0), n, fa, fb, epi);
+            }
+          cz ^= 1;
+        } else {
+          // last half-slice: Z = Z_last, Q = G1^T
+          for (int i = threadIdx.x; i < n * n1; i += BW * 64) {
+            const int r = i / n1, c = i - r * n1;
+            const size_t o = (size_t)r * LD + c;
+            const cx<double> v = ldg(G1h + o);
+            const cx<double> z = ldg(Zb[cz] + o);
+            stg(Qb[cz] + o, v);
+            atomicAdd(&sm.rowacc[r], z.re * v.re - z.im * v.im);
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x < n) {
+          const int i = h >> 1;
+          const int k = half_row(threadIdx.x, e);
+          atomicAdd(a.dL_deps + (q.r * (int64_t)a.L + i) * a.N + k,
+                    2.0 * wt * sm.rowacc[threadIdx.x]);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 }  // namespace
 
-const void* large_kernel_ptr() { return (const void*)rgf_fwd_large_kernel; }
+const void* large_kernel_ptr(bool grad) {
+  return grad ? (const void*)rgf_grad_large_kernel : (const void*)rgf_fwd_large_kernel;
+}
 
 TileCfg large_block_tile() { return TileCfg{-1, BW, BS, BC}; }
 
-int large_slot_blocks() { return kSlotBlocks; }
+int large_slot_blocks(bool grad) { return grad ? kGradSlotBlocks : kSlotBlocks; }
 
-hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
-                                double* T_out, int32_t* status_out, char* ws, hipStream_t s) {
-  if (p.ntuples == 0) return hipSuccess;
-  hipError_t err = launch_lead(p, E, ws, s);
-  if (err != hipSuccess) return err;
+static SweepArgs large_args(const Plan& p, const double* E, const double* eps, double* T_out,
+                            int32_t* status_out, char* ws) {
   SweepArgs a;
   memset(&a, 0, sizeof(a));
   a.N = p.N;
@@ -434,7 +660,33 @@ hipError_t launch_forward_large(const Plan& p, const double* E, const double* ep
   a.slots = reinterpret_cast<cx<double>*>(ws + p.off_slots);
   a.slot_mats = p.slot_mats;
   a.ntuples = p.ntuples;
+  return a;
+}
+
+hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
+                                double* T_out, int32_t* status_out, char* ws, hipStream_t s) {
+  if (p.ntuples == 0) return hipSuccess;
+  hipError_t err = launch_lead(p, E, ws, s);
+  if (err != hipSuccess) return err;
+  SweepArgs a = large_args(p, E, eps, T_out, status_out, ws);
   hipLaunchKernelGGL(rgf_fwd_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_large(const Plan& p, const double* E, const double* eps,
+                             const double* dL_dT, double* T_out, double* dL_deps,
+                             int32_t* status_out, char* ws, hipStream_t s) {
+  if (p.ntuples == 0) return hipSuccess;
+  hipError_t err = launch_lead(p, E, ws, s);
+  if (err != hipSuccess) return err;
+  SweepArgs a = large_args(p, E, eps, T_out, status_out, ws);
+  a.dL_dT = dL_dT;
+  a.dL_deps = dL_deps;
+  a.ckpt = reinterpret_cast<cx<double>*>(ws + p.off_ckpt);
+  a.seg = reinterpret_cast<cx<double>*>(ws + p.off_seg);
+  a.stride = (int)p.ckpt_stride;
+  a.n_ckpt = (int)p.n_ckpt;
+  hipLaunchKernelGGL(rgf_grad_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
 """Write the stored oracle values for ribbons wider than N = 256 under
-tests/golden/ (wide_ribbons.txt, large_n480_sampled.txt).
+tests/golden/ (wide_ribbons.txt, large_n480_sampled.txt, wide_grad.txt).
 
 The oracle's dense lead decimation costs about two minutes per energy at
 N = 480 and its sweep about five minutes for L = 8000, too slow to run inside
@@ -9,7 +9,8 @@ disorder realization and energy; the disorder is regenerated from the seed
 by rgf_workloads.disorder.
 
 Run from the repository root:  python tests/golden/make_wide_golden.py
-(about ten minutes on eight cores).
+(about twenty minutes on eight cores); with the argument `grad` it writes
+only wide_grad.txt.
 """
 
 import multiprocessing as mp
@@ -35,6 +36,11 @@ WIDE = [
 # sampled energies (indices into the workload's grid) of the full-size
 # N = 480, L = 8000 ribbon, realization 0
 LARGE_SAMPLES = [100, 700]
+# gradients dT/deps of every site: (N, L, parity, x = E/|t|, w, r)
+GRAD = [
+    (257, 3, 1, 0.41, 0.5, 2570),
+    (480, 4, 0, -0.137, 0.5, 4800),
+]
 
 
 def _wide_task(case):
@@ -61,7 +67,38 @@ def _large_task(j):
     return j, E, O.transmission(N, L, W.T_HOP, W.ETA, E, eps, 0)
 
 
+def _grad_task(case):
+    import oracle as O
+    import rgf_workloads as W
+    N, L, parity, x, w, r = case
+    E = x * abs(W.T_HOP)
+    eps = W.disorder(L, N, w, r=r)
+    T, g = O.transmission_grad(N, L, W.T_HOP, W.ETA, E, eps, parity)
+    return case, E, T, g
+
+
+def write_grad(res):
+    with open(os.path.join(HERE, "wide_grad.txt"), "w") as f:
+        f.write("# dT/deps of every site of ribbons wider than N = 256, t=-2.7 eV,\n")
+        f.write("# eta=1e-8 eV; disorder rgf_workloads.disorder(L, N, w, r); from\n")
+        f.write("# oracle.transmission_grad. A header line per ribbon:\n")
+        f.write("# ribbon N L parity w r E_eV T_oracle, then L*N lines: i k dT/deps_ik\n")
+        for (N, L, parity, x, w, r), E, T, g in res:
+            f.write(f"ribbon {N} {L} {parity} {w} {r} {E:.17e} {T:.17e}\n")
+            for i in range(L):
+                for k in range(N):
+                    f.write(f"{i} {k} {g[i, k]:.17e}\n")
+
+
 def main():
+    if sys.argv[1:] == ["grad"]:   # the gradient file only
+        os.environ["OMP_NUM_THREADS"] = "4"
+        sys.path.insert(0, ROOT)
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(2, initializer=sys.path.insert, initargs=(0, ROOT)) as pool:
+            res = pool.map(_grad_task, GRAD)
+        write_grad(res)
+        return
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     os.environ["MKL_NUM_THREADS"] = "1"
@@ -69,8 +106,10 @@ def main():
     ctx = mp.get_context("spawn")
     with ctx.Pool(8, initializer=sys.path.insert, initargs=(0, ROOT)) as pool:
         large = pool.map_async(_large_task, LARGE_SAMPLES)
+        grad = pool.map_async(_grad_task, GRAD)
         wide = pool.map(_wide_task, WIDE)
         large = large.get()
+        write_grad(grad.get())
         pool.close()
         pool.join()
     with open(os.path.join(HERE, "wide_ribbons.txt"), "w") as f:

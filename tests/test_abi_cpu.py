@@ -141,23 +141,24 @@ def test_widest_supported_and_first_unsupported_width():
 
 
 @pytest.mark.parametrize("N", [257, 480, 512])
-def test_wide_ribbons_fp64_conductance_only(N):
-    """Half-slices above 128 rows are inverted by blocks in FP64; the reverse
-    sweeps (rgf_grad, rgf_ldos) and the FP32 modes report
-    RGF_ERR_UNSUPPORTED for them before anything is enqueued, while N = 256
-    supports every entry point and precision."""
+def test_wide_ribbons_fp64_only(N):
+    """Half-slices above 128 rows are inverted by panels in FP64: the
+    conductance and the gradient plan, while rgf_ldos and the FP32 modes
+    report RGF_ERR_UNSUPPORTED before anything is enqueued. N = 256 supports
+    every entry point and precision."""
     from paper_1107_5300_amd import _lib as L
     lib = L.lib()
     d = L.make_desc(N, 4)
     for prec in (1, 2):
-        assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, prec, 0, 0) == 0
-        assert b"FP64 only" in lib.rgf_last_error_message()
-    assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 1, 0) == 0
-    assert b"reverse sweeps" in lib.rgf_last_error_message()
+        for grad in (0, 1):
+            assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, prec, grad, 0) == 0
+            assert b"FP64 only" in lib.rgf_last_error_message()
+    assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 1, 0) > 0
     rc = lib.rgf_ldos(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
                       ctypes.c_void_p(16), None, 0, None, None, 0, None)
     assert rc == L.RGF_ERR_UNSUPPORTED
-    rc = lib.rgf_grad(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+    assert b"local density of states" in lib.rgf_last_error_message()
+    rc = lib.rgf_grad(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 1,
                       ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 0, None,
                       None, 0, None)
     assert rc == L.RGF_ERR_UNSUPPORTED
@@ -168,6 +169,21 @@ def test_wide_ribbons_fp64_conductance_only(N):
     for prec in (0, 1, 2):
         for grad in (0, 1):
             assert lib.rgf_workspace_bytes(ctypes.byref(narrow), 4, 1, prec, grad, 0) > 0
+
+
+def test_wide_gradient_workspace_layout():
+    """The wide gradient's workspace: 45 blocks of 128 x 128 complex128 per
+    slot plus, per slot, two 256 x 256 restart matrices per checkpoint and
+    per segment entry (stride s, ceil(2L/s) checkpoints)."""
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    d = L.make_desc(480, 8)
+    full = 256 * 256 * 16
+    for stride, nck in ((4, 4), (16, 1)):
+        one = lib.rgf_workspace_bytes(ctypes.byref(d), 1, 1, 0, 1, stride)
+        two = lib.rgf_workspace_bytes(ctypes.byref(d), 1, 2, 0, 1, stride)  # two tuples
+        per_slot = 45 * 128 * 128 * 16 + (nck + stride) * 2 * full
+        assert per_slot <= two - one <= per_slot + 3 * 256, (stride, two - one, per_slot)
 
 
 def test_wide_ribbon_workspace_scales_with_grid():

@@ -2,10 +2,12 @@
 inverted by the panel Gauss-Jordan in the workspace) through the C ABI.
 
 Stored oracle values (tests/golden/make_wide_golden.py, oracle/ only) for
-widths 257..512 and the full-size N = 480, L = 8000 ribbon on sampled
-energies; closed-form and invariant checks (quantised pristine conductance,
-T(t) = T(-t), 0 <= T <= M(E)) at any size. Bars as for the narrow path:
-1e-9 relative on short ribbons, 1e-6 absolute at full size.
+widths 257..512, the full-size N = 480, L = 8000 ribbon on sampled energies
+and the gradient dT/deps of every site at N = 257 and 480; closed-form and
+invariant checks (quantised pristine conductance, T(t) = T(-t),
+0 <= T <= M(E)) at any size. Bars as for the narrow path: 1e-9 relative on
+short ribbons (gradients 1e-8 relative to max(1, max|dT/deps|)), 1e-6
+absolute at full size.
 """
 
 import os
@@ -209,3 +211,92 @@ def test_large_n480_full_length_sampled(P):
         assert E == Es_all[int(j)]
         _say("  oracle E index", int(j), want, got[0, k])
         assert abs(got[0, k] - want) <= 1e-6
+
+
+# ------------------------------------------------------------------ gradients
+
+def _grad_rows():
+    path = os.path.join(HERE, "golden", "wide_grad.txt")
+    out, cur = [], None
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("#"):
+                continue
+            f = ln.split()
+            if f[0] == "ribbon":
+                cur = dict(N=int(f[1]), L=int(f[2]), parity=int(f[3]), w=float(f[4]),
+                           r=int(f[5]), E=float(f[6]), T=float(f[7]))
+                cur["g"] = np.zeros((cur["L"], cur["N"]))
+                out.append(cur)
+            else:
+                cur["g"][int(f[0]), int(f[1])] = float(f[2])
+    return out
+
+
+def _grad(P, N, L, parity, Es, eps, w, stride=0):
+    import torch
+    t = lambda x: torch.tensor(np.asarray(x, dtype=np.float64), device="cuda")
+    T, g, st = P.grad(P.Ribbon(N, L, parity, W.T_HOP, W.ETA), t(Es), t(eps), t(w),
+                      ckpt_stride=stride, return_status=True)
+    torch.cuda.synchronize()
+    return T.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_wide_grad_matches_oracle(P, k):
+    """dT/deps of every site against the oracle's forward-backward gradient."""
+    c = _grad_rows()[k]
+    N, L = c["N"], c["L"]
+    _say("wide grad", N, L, c["parity"])
+    eps = W.disorder(L, N, c["w"], r=c["r"])
+    T, g, st = _grad(P, N, L, c["parity"], [c["E"]], eps[None], [[1.0]])
+    assert (st == 0).all()
+    assert abs(T[0, 0] - c["T"]) <= 1e-9 * max(1.0, abs(c["T"]))
+    scale = max(1.0, np.abs(c["g"]).max())
+    assert np.abs(g[0] - c["g"]).max() <= 1e-8 * scale, np.abs(g[0] - c["g"]).max()
+
+
+def test_wide_grad_strides_and_weights(P):
+    """Checkpoint strides give the same gradient; several energies and
+    realizations in one call give the weighted sum of single-energy calls."""
+    N, L = 300, 5
+    eps = W.disorder_batch(L, N, 0.5, 2)
+    Es = np.array([-0.31, 0.27]) * abs(W.T_HOP)
+    w = np.array([[0.7, -1.3], [2.0, 0.4]])
+    _say("wide grad strides", N, L)
+    T0, g0, st = _grad(P, N, L, 0, Es, eps, w)
+    assert (st == 0).all()
+    for stride in (1, 3, 10):
+        T1, g1, _ = _grad(P, N, L, 0, Es, eps, w, stride=stride)
+        assert np.abs(g1 - g0).max() <= 1e-12 * max(1.0, np.abs(g0).max())
+        assert np.abs(T1 - T0).max() <= 1e-13 * max(1.0, np.abs(T0).max())
+    want = np.zeros_like(g0)
+    for r in range(2):
+        for j in range(2):
+            _, gj, _ = _grad(P, N, L, 0, [Es[j]], eps[r:r + 1], [[1.0]])
+            want[r] += w[r, j] * gj[0]
+    assert np.abs(g0 - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_wide_grad_finite_differences(P):
+    """N = 480: the gradient against central differences of the GPU
+    forward sweep (h = 1e-6 |t|) on seeded sites."""
+    N, L = 480, 4
+    eps = W.disorder(L, N, 0.5, r=77)
+    E = 0.21 * abs(W.T_HOP)
+    _, g, st = _grad(P, N, L, 0, [E], eps[None], [[1.0]])
+    assert (st == 0).all()
+    h = 1e-6 * abs(W.T_HOP)
+    sites = W.fd_sites(L, N, count=8, seed=5)
+    batch = []
+    for i, k in sites:
+        for sgn in (1.0, -1.0):
+            e2 = eps.copy()
+            e2[i, k] += sgn * h
+            batch.append(e2)
+    _say("wide grad fd", len(sites))
+    Tfd, st2 = _gpu_T(P, N, L, 0, W.T_HOP, [E], np.stack(batch))
+    assert (st2 == 0).all()
+    for n_, (i, k) in enumerate(sites):
+        fd = (Tfd[2 * n_, 0] - Tfd[2 * n_ + 1, 0]) / (2 * h)
+        assert abs(fd - g[0, i, k]) <= 1e-6 + 1e-4 * abs(g[0, i, k]), (i, k, fd, g[0, i, k])
