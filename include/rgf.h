@@ -66,10 +66,9 @@ typedef struct {
  * one workgroup's registers and support every entry point and precision.
  * Wider ribbons (RGF_TILE_MAX_WIDTH < N <= RGF_MAX_WIDTH) keep the
  * half-slice matrices in the workspace (Gauss-Jordan by column panels with
- * partial pivoting over the full height) and support FP64 only:
- * rgf_conductance, rgf_conductance_batched, rgf_grad, rgf_lead_self_energy
- * and rgf_autotune (nothing to tune) with RGF_PREC_FP64; rgf_ldos and the
- * FP32 modes return RGF_ERR_UNSUPPORTED for them. */
+ * partial pivoting over the full height) and support FP64 only: every entry
+ * point with RGF_PREC_FP64 (rgf_autotune has nothing to tune); the FP32
+ * modes return RGF_ERR_UNSUPPORTED for them. */
 #define RGF_TILE_MAX_WIDTH 256
 
 /* Arithmetic of the slice recursion. The lead self-energies, the running

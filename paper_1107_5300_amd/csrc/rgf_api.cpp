@@ -308,18 +308,14 @@ int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_e
   Plan p;
   int st = make_plan(desc, n_energies, n_real, precision, 1, ckpt_stride, &p);
   if (st != RGF_OK) return st;
-  if (p.large)
-    return fail(RGF_ERR_UNSUPPORTED,
-                "width_n = %d: the local density of states supports half-slices of at most "
-                "%d rows (width_n <= %d)",
-                p.N, kTileMaxRows, 2 * kTileMaxRows);
   if (n_energies > 0) {
     if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
     if (!ldos_out) return fail(RGF_ERR_INVALID_ARG, "ldos_out is NULL");
   }
   st = check_ws(p, workspace, workspace_bytes);
   if (st != RGF_OK) return st;
-  hipError_t e = launch_ldos(p, energies_ev, onsite_eps_ev, ldos_out, T_out, status_out,
+  hipError_t e = (p.large ? launch_ldos_large : launch_ldos)(
+      p, energies_ev, onsite_eps_ev, ldos_out, T_out, status_out,
                              (char*)workspace, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e);
   return RGF_OK;

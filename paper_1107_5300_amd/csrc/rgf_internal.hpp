@@ -96,12 +96,15 @@ const void* grad_kernel_ptr(const TileCfg& t, int precision);
 // Matrix buffers (NP x NP complex128) per persistent slot.
 int slot_matrices(int precision, bool grad);
 
-// Blocked forward sweep and gradient for kTileMaxRows < n <= kLargeLd (FP64).
+// Blocked forward sweep, gradient and local density of states for
+// kTileMaxRows < n <= kLargeLd (FP64).
 hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
                                 double* T_out, int32_t* status_out, char* ws, hipStream_t s);
 hipError_t launch_grad_large(const Plan& p, const double* E, const double* eps,
                              const double* dL_dT, double* T_out, double* dL_deps,
                              int32_t* status_out, char* ws, hipStream_t s);
+hipError_t launch_ldos_large(const Plan& p, const double* E, const double* eps, double* ldos,
+                             double* T_out, int32_t* status_out, char* ws, hipStream_t s);
 const void* large_kernel_ptr(bool grad);
 // Register tiling of the blocked kernels' elimination panels (id -1: not a
 // table entry), and their buffers per slot in units of kTileMaxRows^2

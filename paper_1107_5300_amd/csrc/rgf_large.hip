@@ -400,6 +400,42 @@ __device__ __forceinline__ int tuple_status(const SweepArgs& a, const Tuple& q, 
   return st;
 }
 
+// Forward sweep that stores the restart state (g_h, G1_h) after every
+// `stride` half-slices into ck[1..] (the state at h = 0 is rebuilt from the
+// leads). Leaves g_{H-1} in Kb[(H-1) & 1] and G1_{H-1} in G1b[(H-1) & 1].
+__device__ __forceinline__ void large_forward_ckpt(const SweepArgs& a, const Tuple& q,
+                                                   cx<double>* const (&Kb)[2],
+                                                   cx<double>* const (&G1b)[2], cx<double>* X,
+                                                   cx<double>* Xp, cx<double>* ck,
+                                                   cx<double> (&A)[BS][BC], LargeSmem& sm) {
+  const int H = 2 * a.L;
+  for (int h = 0; h < H; ++h) {
+    large_step(a, q, h, Kb[(h + 1) & 1], Kb[h & 1], G1b[(h + 1) & 1], G1b[h & 1], X, Xp, A, sm);
+    if ((h + 1) % a.stride == 0 && h + 1 < H) {
+      cx<double>* c = ck + (size_t)((h + 1) / a.stride) * 2 * FULL;
+      for (size_t i = threadIdx.x; i < FULL; i += BW * 64) {
+        stg(c + i, ldg(Kb[h & 1] + i));
+        stg(c + FULL + i, ldg(G1b[h & 1] + i));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Recompute (g_h, G1_h) for h0 <= h < h1 into the segment buffer sg (pairs
+// of full matrices) from restart state sgi (from the leads for sgi = 0).
+__device__ __forceinline__ void large_recompute(const SweepArgs& a, const Tuple& q, int sgi,
+                                                int h0, int h1, const cx<double>* ck,
+                                                cx<double>* sg, cx<double>* X, cx<double>* Xp,
+                                                cx<double> (&A)[BS][BC], LargeSmem& sm) {
+  for (int h = h0; h < h1; ++h) {
+    const int j = h - h0;
+    const cx<double>* Kp = (j == 0) ? ck + (size_t)sgi * 2 * FULL : sg + (size_t)(j - 1) * 2 * FULL;
+    cx<double>* Ko = sg + (size_t)j * 2 * FULL;
+    large_step(a, q, h, Kp, Ko, Kp + FULL, Ko + FULL, X, Xp, A, sm);
+  }
+}
+
 __global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) {
   __shared__ LargeSmem sm;
   cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * (BP * BP);
@@ -439,8 +475,8 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) 
 __global__ __launch_bounds__(BW * 64, 2) void rgf_grad_large_kernel(SweepArgs a) {
   __shared__ LargeSmem sm;
   cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * (BP * BP);
-  cx<double>* Kb[2] = {slot, slot + FULL};
-  cx<double>* G1b[2] = {slot + 2 * FULL, slot + 3 * FULL};
+  cx<double>* const Kb[2] = {slot, slot + FULL};
+  cx<double>* const G1b[2] = {slot + 2 * FULL, slot + 3 * FULL};
   cx<double>* X = slot + 4 * FULL;
   cx<double>* Y = slot + 5 * FULL;
   cx<double>* Sb = slot + 6 * FULL;
@@ -461,19 +497,7 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_grad_large_kernel(SweepArgs a)
     __syncthreads();
     cx<double> A[BS][BC];
 
-    // ---- forward sweep, restart states after every stride half-slices
-    for (int h = 0; h < H; ++h) {
-      large_step(a, q, h, Kb[(h + 1) & 1], Kb[h & 1], G1b[(h + 1) & 1], G1b[h & 1], X, Xp, A,
-                 sm);
-      if ((h + 1) % a.stride == 0 && h + 1 < H) {
-        cx<double>* c = ck + (size_t)((h + 1) / a.stride) * 2 * FULL;
-        for (size_t i = threadIdx.x; i < FULL; i += BW * 64) {
-          stg(c + i, ldg(Kb[h & 1] + i));
-          stg(c + FULL + i, ldg(G1b[h & 1] + i));
-        }
-        __syncthreads();
-      }
-    }
+    large_forward_ckpt(a, q, Kb, G1b, X, Xp, ck, A, sm);
     const cx<double>* Klast = Kb[(H - 1) & 1];
     const double T = large_trace(a, q, G1b[(H - 1) & 1], Y, Sb, sm);
     const int st = tuple_status(a, q, T, sm);
@@ -537,12 +561,7 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_grad_large_kernel(SweepArgs a)
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
       const int h0 = sgi * a.stride;
       const int h1 = min(H, h0 + a.stride);
-      for (int h = h0; h < h1; ++h) {
-        const int j = h - h0;
-        const cx<double>* Kp = (j == 0) ? ck + (size_t)sgi * 2 * FULL : sg + (size_t)(j - 1) * 2 * FULL;
-        cx<double>* Ko = sg + (size_t)j * 2 * FULL;
-        large_step(a, q, h, Kp, Ko, Kp + FULL, Ko + FULL, X, Xp, A, sm);
-      }
+      large_recompute(a, q, sgi, h0, h1, ck, sg, X, Xp, A, sm);
       for (int h = h1 - 1; h >= h0; --h) {
         const cx<double>* gh = sg + (size_t)(h - h0) * 2 * FULL;
         const cx<double>* G1h = gh + FULL;
@@ -628,6 +647,132 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_grad_large_kernel(SweepArgs a)
   }
 }
 
+// Local density of states -Im G_ss / pi of every site (rgf_ldos.hip's
+// backward sweep of the diagonal blocks, Dyson's equation cut between
+// half-slices):
+//   F_{H-1} = g_{H-1},   F_h = g_h + g_h V,   V = (C_h F_{h+1} C_h^T) g_h,
+// on workspace-resident matrices. V is formed from all of F_{h+1} before
+// F_h overwrites it, so one F buffer serves (row-major; F and g symmetric).
+__global__ __launch_bounds__(BW * 64, 2) void rgf_ldos_large_kernel(SweepArgs a) {
+  constexpr double kInvPi = 0.31830988618379067154;
+  __shared__ LargeSmem sm;
+  cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * (BP * BP);
+  cx<double>* const Kb[2] = {slot, slot + FULL};
+  cx<double>* const G1b[2] = {slot + 2 * FULL, slot + 3 * FULL};
+  cx<double>* X = slot + 4 * FULL;
+  cx<double>* Y = slot + 5 * FULL;
+  cx<double>* F = slot + 7 * FULL;
+  cx<double>* V = slot + 9 * FULL;
+  cx<double>* Xp = slot + 11 * FULL;
+  cx<double>* ck = a.ckpt + (size_t)blockIdx.x * a.n_ckpt * 2 * FULL;
+  cx<double>* sg = a.seg + (size_t)blockIdx.x * a.stride * 2 * FULL;
+  const int H = 2 * a.L;
+
+  for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
+    const Tuple q = make_tuple_(a, tau);
+    if (threadIdx.x == 0) sm.flag = 0;
+    __syncthreads();
+    cx<double> A[BS][BC];
+    double* out = a.ldos + tau * (int64_t)a.L * a.N;  // [L][N] of this tuple
+
+    large_forward_ckpt(a, q, Kb, G1b, X, Xp, ck, A, sm);
+    const cx<double>* Klast = Kb[(H - 1) & 1];
+    const double T = large_trace(a, q, G1b[(H - 1) & 1], Y, nullptr, sm);
+    const int st = tuple_status(a, q, T, sm);
+    if (threadIdx.x == 0) {
+      if (a.T_out) a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
+      if (a.status) a.status[tau] = st;
+    }
+    if (st != RGF_TUPLE_OK) {
+      for (int64_t i = threadIdx.x; i < (int64_t)a.L * a.N; i += BW * 64)
+        out[i] = __builtin_nan("");
+      __syncthreads();
+      continue;
+    }
+
+    // ---- last half-slice: F = g_{H-1}
+    {
+      const int e = half_parity(H - 1, a.parity);
+      const int n = half_size(a.N, e);
+      for (int i = threadIdx.x; i < n * n; i += BW * 64) {
+        const int r = i / n, c = i - r * n;
+        stg(F + (size_t)r * LD + c, ldg(Klast + (size_t)r * LD + c));
+      }
+      if (threadIdx.x < n)
+        out[(int64_t)((H - 1) >> 1) * a.N + half_row(threadIdx.x, e)] =
+            -ldg(Klast + (size_t)threadIdx.x * LD + threadIdx.x).im * kInvPi;
+      __syncthreads();
+    }
+
+    // ---- backward over segments
+    const int nseg = (H + a.stride - 1) / a.stride;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int h0 = sgi * a.stride;
+      const int h1 = min(H, h0 + a.stride);
+      large_recompute(a, q, sgi, h0, h1, ck, sg, X, Xp, A, sm);
+      for (int h = min(h1, H - 1) - 1; h >= h0; --h) {
+        const cx<double>* gh = sg + (size_t)(h - h0) * 2 * FULL;
+        const int e = half_parity(h, a.parity);
+        const int n = half_size(a.N, e);
+        const int en = half_parity(h + 1, a.parity);
+        const int nn = half_size(a.N, en);
+        const double t2 = a.t * a.t;
+        const bool odd = (h & 1) != 0;
+        // rows b of half-slice h+1 that row k of half-slice h bonds to:
+        // h odd (R_i -> L_{i+1}): b = k; h even (L_i -> R_i): k + 1 - eR, k - eR
+        auto nb0 = [&](int k) { return odd ? k : k + 1 - en; };
+        auto nb1 = [&](int k) { return odd ? -1 : k - en; };
+        // W[r][k] = t^2 sum_{b ~ r, b' ~ k} F[b][b']
+        auto fa_w = [&](int r, int k) -> cx<double> {
+          const int rb[2] = {nb0(r), nb1(r)};
+          const int kb2[2] = {nb0(k), nb1(k)};
+          cx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (kb2[u] < 0 || kb2[u] >= nn) continue;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              if (rb[v] < 0 || rb[v] >= nn) continue;
+              acc = cadd(acc, ldg(F + (size_t)kb2[u] * LD + rb[v]));
+            }
+          }
+          return cscale(acc, t2);
+        };
+        for (int r0 = 0; r0 < n; r0 += BP)
+          for (int c0 = 0; c0 < n; c0 += BP) {
+            auto fa = [&](int r, int k) -> cx<double> { return fa_w(r0 + r, k); };
+            auto fb = [&](int k, int c) -> cx<double> {
+              return ldg(gh + (size_t)k * LD + c0 + c);
+            };
+            auto epi = [&](int r, int c, cx<double> v, bool ok) {
+              if (ok) stg(V + (size_t)(r0 + r) * LD + c0 + c, v);
+            };
+            gemm_mfma<BW, BP>(min(BP, n - r0), min(BP, n - c0), n, fa, fb, epi);
+          }
+        __syncthreads();
+        for (int r0 = 0; r0 < n; r0 += BP)
+          for (int c0 = 0; c0 < n; c0 += BP) {
+            auto fa = [&](int r, int k) -> cx<double> {
+              return ldg(gh + (size_t)k * LD + r0 + r);
+            };
+            auto fb = [&](int k, int c) -> cx<double> {
+              return ldg(V + (size_t)k * LD + c0 + c);
+            };
+            auto epi = [&](int r, int c, cx<double> v, bool ok) {
+              if (!ok) return;
+              const int rr = r0 + r, cc = c0 + c;
+              v = cadd(v, ldg(gh + (size_t)rr * LD + cc));
+              stg(F + (size_t)rr * LD + cc, v);
+              if (rr == cc) out[(int64_t)(h >> 1) * a.N + half_row(rr, e)] = -v.im * kInvPi;
+            };
+            gemm_mfma<BW, BP>(min(BP, n - r0), min(BP, n - c0), n, fa, fb, epi);
+          }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 }  // namespace
 
 const void* large_kernel_ptr(bool grad) {
@@ -687,6 +832,21 @@ hipError_t launch_grad_large(const Plan& p, const double* E, const double* eps,
   a.stride = (int)p.ckpt_stride;
   a.n_ckpt = (int)p.n_ckpt;
   hipLaunchKernelGGL(rgf_grad_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ldos_large(const Plan& p, const double* E, const double* eps, double* ldos,
+                             double* T_out, int32_t* status_out, char* ws, hipStream_t s) {
+  if (p.ntuples == 0) return hipSuccess;
+  hipError_t err = launch_lead(p, E, ws, s);
+  if (err != hipSuccess) return err;
+  SweepArgs a = large_args(p, E, eps, T_out, status_out, ws);
+  a.ckpt = reinterpret_cast<cx<double>*>(ws + p.off_ckpt);
+  a.seg = reinterpret_cast<cx<double>*>(ws + p.off_seg);
+  a.stride = (int)p.ckpt_stride;
+  a.n_ckpt = (int)p.n_ckpt;
+  a.ldos = ldos;
+  hipLaunchKernelGGL(rgf_ldos_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 """Write the stored oracle values for ribbons wider than N = 256 under
-tests/golden/ (wide_ribbons.txt, large_n480_sampled.txt, wide_grad.txt).
+tests/golden/ (wide_ribbons.txt, large_n480_sampled.txt, wide_grad.txt,
+wide_ldos.txt).
 
 The oracle's dense lead decimation costs about two minutes per energy at
 N = 480 and its sweep about five minutes for L = 8000, too slow to run inside
@@ -9,8 +10,8 @@ disorder realization and energy; the disorder is regenerated from the seed
 by rgf_workloads.disorder.
 
 Run from the repository root:  python tests/golden/make_wide_golden.py
-(about twenty minutes on eight cores); with the argument `grad` it writes
-only wide_grad.txt.
+(about twenty minutes on eight cores); with the argument `grad` or `ldos`
+it writes only wide_grad.txt or wide_ldos.txt.
 """
 
 import multiprocessing as mp
@@ -67,6 +68,35 @@ def _large_task(j):
     return j, E, O.transmission(N, L, W.T_HOP, W.ETA, E, eps, 0)
 
 
+# local density of states of every site: (N, L, parity, x = E/|t|, w, r)
+LDOS = [
+    (257, 3, 0, -0.23, 0.5, 2571),
+    (480, 4, 1, 0.18, 0.5, 4801),
+]
+
+
+def _ldos_task(case):
+    import oracle as O
+    import rgf_workloads as W
+    N, L, parity, x, w, r = case
+    E = x * abs(W.T_HOP)
+    eps = W.disorder(L, N, w, r=r)
+    return case, E, O.ldos(N, L, W.T_HOP, W.ETA, E, eps, parity)
+
+
+def write_ldos(res):
+    with open(os.path.join(HERE, "wide_ldos.txt"), "w") as f:
+        f.write("# -Im G_ss/pi of every site of ribbons wider than N = 256, t=-2.7 eV,\n")
+        f.write("# eta=1e-8 eV; disorder rgf_workloads.disorder(L, N, w, r); from\n")
+        f.write("# oracle.ldos. A header line per ribbon:\n")
+        f.write("# ribbon N L parity w r E_eV, then L*N lines: i k rho_ik (1/eV)\n")
+        for (N, L, parity, x, w, r), E, rho in res:
+            f.write(f"ribbon {N} {L} {parity} {w} {r} {E:.17e}\n")
+            for i in range(L):
+                for k in range(N):
+                    f.write(f"{i} {k} {rho[i, k]:.17e}\n")
+
+
 def _grad_task(case):
     import oracle as O
     import rgf_workloads as W
@@ -91,13 +121,15 @@ def write_grad(res):
 
 
 def main():
-    if sys.argv[1:] == ["grad"]:   # the gradient file only
+    if sys.argv[1:] in (["grad"], ["ldos"]):   # one file only
         os.environ["OMP_NUM_THREADS"] = "4"
         sys.path.insert(0, ROOT)
         ctx = mp.get_context("spawn")
         with ctx.Pool(2, initializer=sys.path.insert, initargs=(0, ROOT)) as pool:
-            res = pool.map(_grad_task, GRAD)
-        write_grad(res)
+            if sys.argv[1] == "grad":
+                write_grad(pool.map(_grad_task, GRAD))
+            else:
+                write_ldos(pool.map(_ldos_task, LDOS))
         return
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
@@ -107,9 +139,11 @@ def main():
     with ctx.Pool(8, initializer=sys.path.insert, initargs=(0, ROOT)) as pool:
         large = pool.map_async(_large_task, LARGE_SAMPLES)
         grad = pool.map_async(_grad_task, GRAD)
+        ldos = pool.map_async(_ldos_task, LDOS)
         wide = pool.map(_wide_task, WIDE)
         large = large.get()
         write_grad(grad.get())
+        write_ldos(ldos.get())
         pool.close()
         pool.join()
     with open(os.path.join(HERE, "wide_ribbons.txt"), "w") as f:

@@ -142,10 +142,10 @@ def test_widest_supported_and_first_unsupported_width():
 
 @pytest.mark.parametrize("N", [257, 480, 512])
 def test_wide_ribbons_fp64_only(N):
-    """Half-slices above 128 rows are inverted by panels in FP64: the
-    conductance and the gradient plan, while rgf_ldos and the FP32 modes
-    report RGF_ERR_UNSUPPORTED before anything is enqueued. N = 256 supports
-    every entry point and precision."""
+    """Half-slices above 128 rows are inverted by panels in FP64: every entry
+    point plans with RGF_PREC_FP64, while the FP32 modes report
+    RGF_ERR_UNSUPPORTED before anything is enqueued. N = 256 supports every
+    entry point and precision."""
     from paper_1107_5300_amd import _lib as L
     lib = L.lib()
     d = L.make_desc(N, 4)
@@ -154,10 +154,13 @@ def test_wide_ribbons_fp64_only(N):
             assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, prec, grad, 0) == 0
             assert b"FP64 only" in lib.rgf_last_error_message()
     assert lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 1, 0) > 0
-    rc = lib.rgf_ldos(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+    rc = lib.rgf_ldos(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 1,
                       ctypes.c_void_p(16), None, 0, None, None, 0, None)
     assert rc == L.RGF_ERR_UNSUPPORTED
-    assert b"local density of states" in lib.rgf_last_error_message()
+    assert b"FP64 only" in lib.rgf_last_error_message()
+    rc = lib.rgf_ldos(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+                      ctypes.c_void_p(16), None, 0, None, None, 0, None)
+    assert rc == L.RGF_ERR_WORKSPACE   # FP64 plans; the NULL workspace is too small
     rc = lib.rgf_grad(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 1,
                       ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 0, None,
                       None, 0, None)

@@ -2,8 +2,9 @@
 inverted by the panel Gauss-Jordan in the workspace) through the C ABI.
 
 Stored oracle values (tests/golden/make_wide_golden.py, oracle/ only) for
-widths 257..512, the full-size N = 480, L = 8000 ribbon on sampled energies
-and the gradient dT/deps of every site at N = 257 and 480; closed-form and
+widths 257..512, the full-size N = 480, L = 8000 ribbon on sampled energies,
+and the gradient dT/deps and the local density of states of every site at
+N = 257 and 480; closed-form and
 invariant checks (quantised pristine conductance, T(t) = T(-t),
 0 <= T <= M(E)) at any size. Bars as for the narrow path: 1e-9 relative on
 short ribbons (gradients 1e-8 relative to max(1, max|dT/deps|)), 1e-6
@@ -300,3 +301,67 @@ def test_wide_grad_finite_differences(P):
     for n_, (i, k) in enumerate(sites):
         fd = (Tfd[2 * n_, 0] - Tfd[2 * n_ + 1, 0]) / (2 * h)
         assert abs(fd - g[0, i, k]) <= 1e-6 + 1e-4 * abs(g[0, i, k]), (i, k, fd, g[0, i, k])
+
+
+# ------------------------------------------------------------------ LDOS
+
+def _ldos_rows():
+    out, cur = [], None
+    with open(os.path.join(HERE, "golden", "wide_ldos.txt")) as fh:
+        for ln in fh:
+            if ln.startswith("#"):
+                continue
+            f = ln.split()
+            if f[0] == "ribbon":
+                cur = dict(N=int(f[1]), L=int(f[2]), parity=int(f[3]), w=float(f[4]),
+                           r=int(f[5]), E=float(f[6]))
+                cur["rho"] = np.zeros((cur["L"], cur["N"]))
+                out.append(cur)
+            else:
+                cur["rho"][int(f[0]), int(f[1])] = float(f[2])
+    return out
+
+
+def _ldos(P, N, L, parity, Es, eps=None, stride=0):
+    import torch
+    rib = P.Ribbon(N, L, parity, W.T_HOP, W.ETA)
+    E = torch.tensor(np.asarray(Es, dtype=np.float64), device="cuda")
+    ep = None if eps is None else torch.tensor(np.asarray(eps), device="cuda")
+    rho, T, st = P.ldos(rib, E, ep, ckpt_stride=stride, return_T=True, return_status=True)
+    torch.cuda.synchronize()
+    return rho.cpu().numpy(), T.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_wide_ldos_matches_oracle(P, k):
+    """-Im G_ss/pi of every site against the oracle, 1e-9 relative to
+    max(1, max rho)."""
+    c = _ldos_rows()[k]
+    N, L = c["N"], c["L"]
+    _say("wide ldos", N, L, c["parity"])
+    eps = W.disorder(L, N, c["w"], r=c["r"])
+    rho, _, st = _ldos(P, N, L, c["parity"], [c["E"]], eps[None])
+    assert (st == 0).all()
+    scale = max(1.0, np.abs(c["rho"]).max())
+    assert np.abs(rho[0, 0] - c["rho"]).max() <= 1e-9 * scale
+
+
+def test_wide_ldos_pristine_period_and_strides(P):
+    """A pristine N = 480 ribbon between identical leads is a piece of the
+    infinite ribbon: the LDOS repeats every two slices (the bond pattern's
+    period) and is non-negative; checkpoint strides agree; T equals the
+    conductance call's."""
+    N, L = 480, 6
+    Es = np.array([0.137, -0.21]) * abs(W.T_HOP)
+    _say("wide ldos pristine", N, L)
+    rho, T, st = _ldos(P, N, L, 0, Es)
+    assert (st == 0).all()
+    scale = np.abs(rho).max()
+    assert (rho >= -1e-9 * scale).all()
+    for i in range(L - 2):
+        assert np.abs(rho[0, :, i] - rho[0, :, i + 2]).max() <= 1e-8 * scale
+    for stride in (1, 5):
+        r2, _, _ = _ldos(P, N, L, 0, Es, stride=stride)
+        assert np.abs(r2 - rho).max() <= 1e-12 * scale
+    T2, _ = _gpu_T(P, N, L, 0, W.T_HOP, Es)
+    assert np.abs(T - T2).max() <= 1e-12 * max(1.0, np.abs(T2).max())
