@@ -29,6 +29,11 @@ Parity status per function (see the pins in tests/test_oracle_*.py):
   ldos_bf                pinned: closed-form LDOS of the infinite 1D chain
                          (the N = 2 ribbon), non-negativity
   ldos                   pinned: == ldos_bf on tiny ribbons
+  channel_transmission_bf
+                         pinned: pristine ribbons transmit every open channel
+                         fully (T_i = 1, M(E) channels), 0 <= T_i <= 1, sum
+                         T_i = transmission_bf
+  channel_transmission   pinned: == channel_transmission_bf on tiny ribbons
 """
 
 from .rgf_oracle import (  # noqa: F401
@@ -43,6 +48,8 @@ from .rgf_oracle import (  # noqa: F401
     transmission_rl,
     ldos,
     ldos_bf,
+    channel_transmission,
+    channel_transmission_bf,
     transmission_bf,
     transmission_grad,
     transmission_grad_bf,

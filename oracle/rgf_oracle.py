@@ -36,6 +36,8 @@ __all__ = [
     "transmission_grad_bf",
     "ldos",
     "ldos_bf",
+    "channel_transmission",
+    "channel_transmission_bf",
     "open_channels",
     "half_gap",
     "transmission_sweep",
@@ -430,6 +432,43 @@ def ldos(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
         F = gi + gi @ U @ F @ U.T @ gi
         out[i - 1] = -np.imag(np.diag(F)) / np.pi
     return out
+
+
+# --------------------------------------------------------------------------
+# Transmission per incoming lead channel. Gamma_L is real symmetric and
+# positive semidefinite; its eigenvectors u_i with gamma_i > 0 are the
+# incoming channels of the left lead, and Eq. (2) splits as
+#   T = Tr[Gamma_L G Gamma_R G^dagger] = sum_i gamma_i u_i^T G Gamma_R G^dagger u_i.
+# --------------------------------------------------------------------------
+
+def _channel_split(gl, gr, G, rel_tol):
+    """(gamma_i, T_i) for the eigenpairs of Gamma_L with gamma_i above
+    rel_tol * max gamma, in decreasing gamma."""
+    gl = np.real(0.5 * (gl + gl.conj().T))
+    w, U = np.linalg.eigh(gl)
+    keep = w > rel_tol * max(w.max(), 0.0)
+    w, U = w[keep][::-1], U[:, keep][:, ::-1]
+    M = G @ gr @ G.conj().T
+    Ti = np.array([w[i] * np.real(U[:, i] @ M @ U[:, i]) for i in range(len(w))])
+    return w, Ti
+
+
+def channel_transmission(N, L, t, eta, E, eps=None, parity=0, sigmas=None, rel_tol=1e-6):
+    """(gamma_i, T_i) of the left lead's incoming channels (eigenpairs of
+    Gamma_L whose gamma_i exceeds rel_tol * max gamma; evanescent modes have
+    gamma of order eta), G = G_{1L} from the recursion. sum_i T_i = T."""
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    _, G = transmission(N, L, t, eta, E, eps, parity, sigmas, return_g=True)
+    return _channel_split(_gamma(sigmas[0]), _gamma(sigmas[1]), G, rel_tol)
+
+
+def channel_transmission_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None, rel_tol=1e-6):
+    """channel_transmission with G_{1L} from the full inverse (tiny ribbons)."""
+    if sigmas is None:
+        sigmas = lead_self_energies(N, L, t, eta, E, parity)
+    Gf = np.linalg.inv(_full_matrix(N, L, t, eta, E, eps, parity, sigmas))
+    return _channel_split(_gamma(sigmas[0]), _gamma(sigmas[1]), Gf[:N, (L - 1) * N:], rel_tol)
 
 
 # --------------------------------------------------------------------------
