@@ -48,7 +48,7 @@ extern "C" {
 #endif
 
 #define RGF_ABI_VERSION_MAJOR 1
-#define RGF_ABI_VERSION_MINOR 1
+#define RGF_ABI_VERSION_MINOR 2
 
 /* Ribbon geometry and model constants. */
 typedef struct {
@@ -122,6 +122,25 @@ int rgf_conductance(const rgf_ribbon_desc* desc, const double* energies_ev,
                     int32_t* status_out, void* workspace,
                     size_t workspace_bytes, void* hip_stream);
 
+/* Conductance split over the incoming channels of the left lead (Eq. (2) in
+ * the eigenbasis of Gamma_L): the left lead's P = ceil(N/2) transverse mode
+ * chains each carry at most one channel, with broadening d_p = -2 Im sigma_p
+ * (sigma_p as returned by rgf_lead_modes), and
+ *   T_channel_out[r][e][p] = d_p sum_q d_q |(Phi_L^T G_{1L} Phi_R)_pq|^2,
+ * whose sum over p is T_out[r][e] (Phi the mode vectors on the rows that
+ * bond to each lead). Closed modes give T_p ~ 0 (of order eta). A pristine
+ * ribbon gives T_p = 1 for every open channel.
+ *   T_channel_out [n_real][n_energies][P]; T_out, status_out as in
+ *   rgf_conductance (status_out may be NULL); T_p = NaN for tuples that are
+ *   not RGF_TUPLE_OK. precision must be RGF_PREC_FP64 (else
+ *   RGF_ERR_UNSUPPORTED).
+ * Workspace: rgf_workspace_bytes(desc, n_energies, n_real, precision, 0, 0). */
+int rgf_channel_transmission(const rgf_ribbon_desc* desc, const double* energies_ev,
+                             int64_t n_energies, const double* onsite_eps_ev,
+                             int64_t n_real, int precision, double* T_channel_out,
+                             double* T_out, int32_t* status_out, void* workspace,
+                             size_t workspace_bytes, void* hip_stream);
+
 /* Conductance and the gradient of L = sum_{r,e} dL_dT[r][e] * T[r][e] with
  * respect to every on-site energy (vector-Jacobian product of Eq. (2)
  * through Eqs. (1), (4), (5)):
@@ -183,6 +202,22 @@ int rgf_lead_self_energy(const rgf_ribbon_desc* desc, const double* energies_ev,
                          double* sigma_r_out, int32_t* lead_status_out,
                          int32_t* nl_out, int32_t* nr_out, void* workspace,
                          size_t workspace_bytes, void* hip_stream);
+
+/* Per-mode lead self-energies sigma_p, p = 1..P (P = ceil(N/2) through
+ * n_modes_out; both leads present the same mode chains), from which
+ * Sigma_L = Phi_L diag(sigma) Phi_L^T:
+ *   method 0: Sancho-Rubio decimation (what every sweep uses);
+ *   method 1: mode matching: the closed-form retarded root of each mode
+ *             chain's surface equation (the Bloch-mode solution the paper's
+ *             eigenproblem gives), an independent cross-check.
+ *   sigma_modes_out [n_energies][P][2] interleaved (re, im) float64, or NULL;
+ *   lead_status_out [n_energies] int32 (RGF_TUPLE_*), or NULL.
+ * Pass NULL outputs to query P only. Workspace: rgf_workspace_bytes(desc,
+ * n_energies, 1, RGF_PREC_FP64, 0, 0). */
+int rgf_lead_modes(const rgf_ribbon_desc* desc, const double* energies_ev,
+                   int64_t n_energies, int method, double* sigma_modes_out,
+                   int32_t* lead_status_out, int32_t* n_modes_out, void* workspace,
+                   size_t workspace_bytes, void* hip_stream);
 
 /* Autotuner for the register tiling of the slice recursion (the batching
  * form of the method: tile shape and tuples in flight per compute unit).

@@ -15,6 +15,8 @@ from .rgf import (  # noqa: F401
     ldos,
     RGFConductance,
     lead_self_energy,
+    lead_modes,
+    channel_transmission,
     workspace_bytes,
     version,
     autotune,

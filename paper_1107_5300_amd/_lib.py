@@ -34,6 +34,8 @@ EXPORTED = (
     "rgf_conductance",
     "rgf_grad",
     "rgf_ldos",
+    "rgf_channel_transmission",
+    "rgf_lead_modes",
     "rgf_batched_workspace_bytes",
     "rgf_conductance_batched",
     "rgf_lead_self_energy",
@@ -83,6 +85,12 @@ def _declare(lib):
     lib.rgf_ldos.restype = _int
     lib.rgf_ldos.argtypes = [_pdesc, _vp, _i64, _vp, _i64, _int, _vp, _vp, _i64, _vp, _vp, _sz,
                              _vp]
+    lib.rgf_channel_transmission.restype = _int
+    lib.rgf_channel_transmission.argtypes = [_pdesc, _vp, _i64, _vp, _i64, _int, _vp, _vp, _vp,
+                                             _vp, _sz, _vp]
+    lib.rgf_lead_modes.restype = _int
+    lib.rgf_lead_modes.argtypes = [_pdesc, _vp, _i64, _int, _vp, _vp, ctypes.POINTER(_i32), _vp,
+                                   _sz, _vp]
     lib.rgf_batched_workspace_bytes.restype = _sz
     lib.rgf_batched_workspace_bytes.argtypes = [_pdesc, _i32, _i64, _i64, _int]
     lib.rgf_conductance_batched.restype = _int

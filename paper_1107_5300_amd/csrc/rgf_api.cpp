@@ -279,6 +279,49 @@ int rgf_conductance(const rgf_ribbon_desc* desc, const double* energies_ev,
   return RGF_OK;
 }
 
+int rgf_channel_transmission(const rgf_ribbon_desc* desc, const double* energies_ev,
+                             int64_t n_energies, const double* onsite_eps_ev, int64_t n_real,
+                             int precision, double* T_channel_out, double* T_out,
+                             int32_t* status_out, void* workspace, size_t workspace_bytes,
+                             void* hip_stream) {
+  Plan p;
+  int st = make_plan(desc, n_energies, n_real, precision, 0, 0, &p);
+  if (st != RGF_OK) return st;
+  if (precision != RGF_PREC_FP64)
+    return fail(RGF_ERR_UNSUPPORTED, "the per-channel transmission runs in FP64 only");
+  if (n_energies == 0) return RGF_OK;
+  if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
+  if (!T_channel_out) return fail(RGF_ERR_INVALID_ARG, "T_channel_out is NULL");
+  if (!T_out) return fail(RGF_ERR_INVALID_ARG, "T_out is NULL");
+  st = check_ws(p, workspace, workspace_bytes);
+  if (st != RGF_OK) return st;
+  hipError_t e = launch_forward(p, energies_ev, onsite_eps_ev, T_out, status_out,
+                                (char*)workspace, (hipStream_t)hip_stream, T_channel_out);
+  if (e != hipSuccess) return hip_fail(e);
+  return RGF_OK;
+}
+
+int rgf_lead_modes(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_energies,
+                   int method, double* sigma_modes_out, int32_t* lead_status_out,
+                   int32_t* n_modes_out, void* workspace, size_t workspace_bytes,
+                   void* hip_stream) {
+  if (method != 0 && method != 1)
+    return fail(RGF_ERR_INVALID_ARG, "method = %d, expected 0 or 1", method);
+  Plan p;
+  int st = make_plan(desc, n_energies, 1, RGF_PREC_FP64, 0, 0, &p);
+  if (st != RGF_OK) return st;
+  if (n_modes_out) *n_modes_out = p.P;
+  if (!sigma_modes_out && !lead_status_out) return RGF_OK;
+  if (n_energies == 0) return RGF_OK;
+  if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
+  st = check_ws(p, workspace, workspace_bytes);
+  if (st != RGF_OK) return st;
+  hipError_t e = launch_lead_modes(p, energies_ev, method, sigma_modes_out, lead_status_out,
+                                   (char*)workspace, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return RGF_OK;
+}
+
 int rgf_grad(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_energies,
              const double* onsite_eps_ev, int64_t n_real, int precision,
              const double* dL_dT, double* T_out, double* dL_deps, int64_t ckpt_stride,
@@ -315,8 +358,8 @@ int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_e
   st = check_ws(p, workspace, workspace_bytes);
   if (st != RGF_OK) return st;
   hipError_t e = (p.large ? launch_ldos_large : launch_ldos)(
-      p, energies_ev, onsite_eps_ev, ldos_out, T_out, status_out,
-                             (char*)workspace, (hipStream_t)hip_stream);
+      p, energies_ev, onsite_eps_ev, ldos_out, T_out, status_out, (char*)workspace,
+      (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e);
   return RGF_OK;
 }

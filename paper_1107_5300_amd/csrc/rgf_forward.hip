@@ -21,7 +21,8 @@ namespace {
 // workgroup per compute unit); narrower tilings ask for three waves per SIMD
 // (two with the refinement's extra tiles) so that several workgroups share a
 // compute unit and hide each other's barrier and memory latency.
-template <typename TJ, bool REFINE, int NW, int S, int C>
+// CHAN: also write the transmission per incoming lead channel (a.tchan).
+template <typename TJ, bool REFINE, int NW, int S, int C, bool CHAN = false>
 __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_fwd_kernel(
     SweepArgs a) {
   constexpr int NP = NW * C;
@@ -40,14 +41,21 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_f
       half_step<TJ, REFINE, NW, S, C>(a, q, h, kb[(h + 1) & 1], kb[h & 1], gbuf, gbuf, rbuf,
                                       A, sm);
     }
-    const double T = trace_T<NW, S, C>(a, q, gbuf, rbuf, A, sm);
-    if (threadIdx.x == 0) {
+    const double T = trace_T<NW, S, C>(a, q, gbuf, rbuf, A, sm, CHAN);
+    if (CHAN || threadIdx.x == 0) {
       int st = a.lstat[q.e];
       if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
       if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
       if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
-      a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
-      if (a.status) a.status[tau] = st;
+      if (threadIdx.x == 0) {
+        a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
+        if (a.status) a.status[tau] = st;
+      }
+      if constexpr (CHAN) {  // T_p = d_p sum_q d_q |S_pq|^2 (block_sum's barriers order rowacc)
+        for (int p = threadIdx.x; p < a.P; p += NW * 64)
+          a.tchan[tau * a.P + p] =
+              (st == RGF_TUPLE_OK) ? -2.0 * q.sig[p].im * sm.rowacc[p] : __builtin_nan("");
+      }
     }
     __syncthreads();
   }
@@ -58,15 +66,16 @@ using FwdKernel = void (*)(SweepArgs);
 struct FwdEntry {
   int NW, S, C;
   FwdKernel k[3];  // by precision: FP64, MIXED, FP32
+  FwdKernel chan;  // FP64 with the per-channel transmission
 };
 
 #define RGF_FWD_ENTRY(NW, S, C)                                              \
   {                                                                          \
-    NW, S, C, {                                                              \
-      rgf_fwd_kernel<double, false, NW, S, C>,                               \
-          rgf_fwd_kernel<float, true, NW, S, C>,                             \
-          rgf_fwd_kernel<float, false, NW, S, C>                             \
-    }                                                                        \
+    NW, S, C,                                                                \
+        {rgf_fwd_kernel<double, false, NW, S, C>,                            \
+         rgf_fwd_kernel<float, true, NW, S, C>,                              \
+         rgf_fwd_kernel<float, false, NW, S, C>},                            \
+        rgf_fwd_kernel<double, false, NW, S, C, true>                        \
   }
 
 const FwdEntry kFwd[] = {
@@ -109,8 +118,8 @@ const void* fwd_kernel_ptr(const TileCfg& t, int precision) {
 }
 
 hipError_t launch_forward(const Plan& p, const double* E, const double* eps, double* T_out,
-                          int32_t* status_out, char* ws, hipStream_t s) {
-  if (p.large) return launch_forward_large(p, E, eps, T_out, status_out, ws, s);
+                          int32_t* status_out, char* ws, hipStream_t s, double* tchan) {
+  if (p.large) return launch_forward_large(p, E, eps, T_out, status_out, ws, s, tchan);
   if (p.ntuples == 0) return hipSuccess;
   hipError_t err = launch_lead(p, E, ws, s);
   if (err != hipSuccess) return err;
@@ -134,8 +143,10 @@ hipError_t launch_forward(const Plan& p, const double* E, const double* eps, dou
   a.slots = reinterpret_cast<cx<double>*>(ws + p.off_slots);
   a.slot_mats = p.slot_mats;
   a.ntuples = p.ntuples;
+  a.tchan = tchan;
   const FwdEntry& f = kFwd[p.tile.id];
-  hipLaunchKernelGGL(f.k[p.precision], dim3(p.grid), dim3(f.NW * 64), 0, s, a);
+  if (tchan && p.precision != RGF_PREC_FP64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tchan ? f.chan : f.k[p.precision], dim3(p.grid), dim3(f.NW * 64), 0, s, a);
   return hipGetLastError();
 }
 

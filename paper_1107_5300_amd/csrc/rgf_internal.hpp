@@ -70,10 +70,18 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
 void set_error(const char* fmt, ...);
 
 // Launchers (enqueue only; return hipError_t).
-hipError_t launch_lead(const Plan& p, const double* E, char* ws, hipStream_t s);
+// method 0: Sancho-Rubio decimation per transverse mode; 1: the closed-form
+// root of each mode chain's surface equation (mode matching).
+hipError_t launch_lead(const Plan& p, const double* E, char* ws, hipStream_t s,
+                       int method = 0);
+// tchan (optional): transmission per incoming lead channel, [nreal][nE][P].
 hipError_t launch_forward(const Plan& p, const double* E, const double* eps,
                           double* T_out, int32_t* status_out, char* ws,
-                          hipStream_t s);
+                          hipStream_t s, double* tchan = nullptr);
+// Per-mode lead self-energies sigma_p ([nE][P] complex128 as (re, im)) by
+// either method, and the lead status.
+hipError_t launch_lead_modes(const Plan& p, const double* E, int method, double* sigma_out,
+                             int32_t* lstat_out, char* ws, hipStream_t s);
 hipError_t launch_export_sigma(const Plan& p, const double* E, double* sl,
                                double* sr, int32_t* lstat_out, char* ws,
                                hipStream_t s);
@@ -99,7 +107,8 @@ int slot_matrices(int precision, bool grad);
 // Blocked forward sweep, gradient and local density of states for
 // kTileMaxRows < n <= kLargeLd (FP64).
 hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
-                                double* T_out, int32_t* status_out, char* ws, hipStream_t s);
+                                double* T_out, int32_t* status_out, char* ws, hipStream_t s,
+                                double* tchan);
 hipError_t launch_grad_large(const Plan& p, const double* E, const double* eps,
                              const double* dL_dT, double* T_out, double* dL_deps,
                              int32_t* status_out, char* ws, hipStream_t s);

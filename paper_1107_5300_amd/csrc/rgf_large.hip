@@ -352,10 +352,12 @@ __device__ __forceinline__ void large_step(const SweepArgs& a, const Tuple& q, i
 
 // T = sum_{p,q} d_p d_q |S_pq|^2 with S = Phi_L^T G Phi_R (G = G_{1L}, n1 x
 // nlast), through Y = G Phi_R; S is also stored (column-major) when Sout is
-// non-null. Every thread returns T.
+// non-null, and the channel sums sum_q d_q |S_pq|^2 are left in
+// sm.rowacc[p] when chan is set. Every thread returns T.
 __device__ __forceinline__ double large_trace(const SweepArgs& a, const Tuple& q,
                                               const cx<double>* G, cx<double>* Y,
-                                              cx<double>* Sout, LargeSmem& sm) {
+                                              cx<double>* Sout, LargeSmem& sm,
+                                              bool chan = false) {
   const int H = 2 * a.L;
   const int n1 = half_size(a.N, half_parity(0, a.parity));
   const int nlast = half_size(a.N, half_parity(H - 1, a.parity));
@@ -372,6 +374,8 @@ __device__ __forceinline__ double large_trace(const SweepArgs& a, const Tuple& q
       };
       gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, a.P - c0), nlast, fa, fb, epi);
     }
+  if (chan)
+    for (int i = threadIdx.x; i < NR; i += BW * 64) sm.rowacc[i] = 0.0;
   __syncthreads();
   double part = 0.0;
   for (int r0 = 0; r0 < a.P; r0 += BP)
@@ -385,6 +389,7 @@ __device__ __forceinline__ double large_trace(const SweepArgs& a, const Tuple& q
         const double dp = -2.0 * q.sig[r0 + r].im, dq = -2.0 * q.sig[c0 + c].im;
         part += dp * dq * (v.re * v.re + v.im * v.im);
         if (Sout) stg(Sout + (size_t)(c0 + c) * LD + r0 + r, v);
+        if (chan) atomicAdd(&sm.rowacc[r0 + r], dq * (v.re * v.re + v.im * v.im));
       };
       gemm_mfma<BW, BP>(min(BP, a.P - r0), min(BP, a.P - c0), n1, fa, fb, epi);
     }
@@ -453,11 +458,16 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) 
     cx<double> A[BS][BC];
     for (int h = 0; h < H; ++h)
       large_step(a, q, h, K, K, G1b[(h + 1) & 1], G1b[h & 1], X, Xp, A, sm);
-    const double T = large_trace(a, q, G1b[(H - 1) & 1], Y, nullptr, sm);
+    const double T = large_trace(a, q, G1b[(H - 1) & 1], Y, nullptr, sm, a.tchan != nullptr);
+    const int st = tuple_status(a, q, T, sm);
     if (threadIdx.x == 0) {
-      const int st = tuple_status(a, q, T, sm);
       a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
       if (a.status) a.status[tau] = st;
+    }
+    if (a.tchan) {  // T_p = d_p sum_q d_q |S_pq|^2 (block_sum's barriers order rowacc)
+      for (int p = threadIdx.x; p < a.P; p += BW * 64)
+        a.tchan[tau * a.P + p] =
+            (st == RGF_TUPLE_OK) ? -2.0 * q.sig[p].im * sm.rowacc[p] : __builtin_nan("");
     }
     __syncthreads();
   }
@@ -809,11 +819,13 @@ static SweepArgs large_args(const Plan& p, const double* E, const double* eps, d
 }
 
 hipError_t launch_forward_large(const Plan& p, const double* E, const double* eps,
-                                double* T_out, int32_t* status_out, char* ws, hipStream_t s) {
+                                double* T_out, int32_t* status_out, char* ws, hipStream_t s,
+                                double* tchan) {
   if (p.ntuples == 0) return hipSuccess;
   hipError_t err = launch_lead(p, E, ws, s);
   if (err != hipSuccess) return err;
   SweepArgs a = large_args(p, E, eps, T_out, status_out, ws);
+  a.tchan = tchan;
   hipLaunchKernelGGL(rgf_fwd_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
   return hipGetLastError();
 }

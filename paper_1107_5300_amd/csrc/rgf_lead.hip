@@ -62,11 +62,31 @@ __device__ __forceinline__ double mmax(const m2& x) {
   return fmax(fmax(cabs1(x.a), cabs1(x.b)), fmax(cabs1(x.c), cabs1(x.d)));
 }
 
-// One block per energy; threads loop over the modes.
+// Principal square root (branch cut on the negative real axis), from the
+// half-angle formulas: sqrt(a) = sqrt((|a| + re)/2) + i sign(im) sqrt((|a| - re)/2),
+// with the smaller component taken as im / (2 * larger) to avoid cancellation.
+__device__ __forceinline__ cx<double> csqrt_principal(cx<double> a) {
+  const double m = hypot(a.re, a.im);
+  if (m == 0.0) return mk(0.0, 0.0);
+  if (a.re >= 0.0) {
+    const double x = sqrt(0.5 * (m + a.re));
+    return mk(x, a.im / (2.0 * x));
+  }
+  const double y = copysign(sqrt(0.5 * (m - a.re)), a.im);
+  return mk(a.im / (2.0 * y), y);
+}
+
+// One block per energy; threads loop over the modes. method 0: decimation;
+// method 1: closed form (mode matching): the surface Green's function of the
+// chain s0 -e- s1 -t- s0' -e- ... solves g = 1 / (z - e^2 / (z - t^2 g)), i.e.
+//   z t^2 g^2 - (z^2 + t^2 - e^2) g + z = 0,
+// whose roots are the two Bloch solutions; the retarded one is the root whose
+// layer-to-layer amplitude |e t g / (z - t^2 g)| is below 1 (decaying or
+// outgoing for eta > 0). For e = 0 the surface site is isolated: g = 1/z.
 __global__ void lead_modes_kernel(int N, int P, double t, double eta,
                                   const double* __restrict__ E,
                                   cx<double>* __restrict__ sigma,
-                                  int32_t* __restrict__ lstat) {
+                                  int32_t* __restrict__ lstat, int method) {
   const int64_t e = blockIdx.x;
   const cx<double> z = mk(E[e], eta);
   const cx<double> zero = mk(0.0, 0.0);
@@ -76,6 +96,27 @@ __global__ void lead_modes_kernel(int N, int P, double t, double eta,
     // e_p = 2t cos(p pi/(N+1)); the middle mode of odd N has cos = 0 exactly
     double ep = middle ? 0.0 : 2.0 * t * cospi((double)p / (double)(N + 1));
     double wp = middle ? 1.0 : 2.0;
+    if (method == 1) {
+      cx<double> g;
+      if (ep == 0.0) {
+        g = crcp(z);
+      } else {
+        const cx<double> z2 = cmul(z, z);
+        const cx<double> b = mk(z2.re + t * t - ep * ep, z2.im);
+        const cx<double> disc = csub(cmul(b, b), cscale(z2, 4.0 * t * t));
+        const cx<double> sq = csqrt_principal(disc);
+        const cx<double> den = crcp(cscale(z, 2.0 * t * t));
+        const cx<double> g1 = cmul(cadd(b, sq), den), g2 = cmul(csub(b, sq), den);
+        const cx<double> d1 = csub(z, cscale(g1, t * t)), d2 = csub(z, cscale(g2, t * t));
+        const double l1 = hypot(g1.re, g1.im) / hypot(d1.re, d1.im);
+        const double l2 = hypot(g2.re, g2.im) / hypot(d2.re, d2.im);
+        g = (l1 <= l2) ? g1 : g2;
+      }
+      const cx<double> sg = cscale(g, wp * t * t);
+      sigma[e * P + (p - 1)] = sg;
+      if (!cfinite(sg)) bad = max(bad, (int)RGF_TUPLE_NONFINITE);
+      continue;
+    }
     // principal layer: sites (s0, s1) joined by e_p; s1 -> s0 of the next layer by t
     m2 h00{zero, mk(ep, 0.0), mk(ep, 0.0), zero};
     m2 alpha{zero, zero, mk(t, 0.0), zero};   // H_{layer, next}
@@ -192,14 +233,14 @@ __global__ void export_sigma_kernel(int P, int ld, int nl, int nr, int64_t nE,
 
 }  // namespace
 
-hipError_t launch_lead(const Plan& p, const double* E, char* ws, hipStream_t s) {
+hipError_t launch_lead(const Plan& p, const double* E, char* ws, hipStream_t s, int method) {
   auto* sigma = reinterpret_cast<cx<double>*>(ws + p.off_sigma);
   auto* phi = reinterpret_cast<double*>(ws + p.off_phi);
   auto* lstat = reinterpret_cast<int32_t*>(ws + p.off_lstat);
   const int ld = p.phi_ld;
   if (p.nE > 0) {
     hipLaunchKernelGGL(lead_modes_kernel, dim3((unsigned)p.nE), dim3(128), 0, s, p.N,
-                       p.P, p.t, p.eta, E, sigma, lstat);
+                       p.P, p.t, p.eta, E, sigma, lstat, method);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -225,6 +266,23 @@ hipError_t launch_export_sigma(const Plan& p, const double* E, double* sl, doubl
     if (err != hipSuccess) return err;
   }
   if (lstat_out && p.nE > 0)
+    err = hipMemcpyAsync(lstat_out, ws + p.off_lstat, p.nE * sizeof(int32_t),
+                         hipMemcpyDeviceToDevice, s);
+  return err;
+}
+
+}  // namespace rgf
+
+namespace rgf {
+
+hipError_t launch_lead_modes(const Plan& p, const double* E, int method, double* sigma_out,
+                             int32_t* lstat_out, char* ws, hipStream_t s) {
+  hipError_t err = launch_lead(p, E, ws, s, method);
+  if (err != hipSuccess || p.nE == 0) return err;
+  if (sigma_out)
+    err = hipMemcpyAsync(sigma_out, ws + p.off_sigma, (size_t)p.nE * p.P * 16,
+                         hipMemcpyDeviceToDevice, s);
+  if (err == hipSuccess && lstat_out)
     err = hipMemcpyAsync(lstat_out, ws + p.off_lstat, p.nE * sizeof(int32_t),
                          hipMemcpyDeviceToDevice, s);
   return err;

@@ -54,6 +54,8 @@ struct SweepArgs {
   int stride, n_ckpt;
   // local density of states only
   double* ldos;             // [nreal][nE][L][N]
+  // transmission per incoming lead channel, or null
+  double* tchan;            // [nreal][nE][P]
 };
 
 template <int NW, int S, int C>
@@ -374,10 +376,13 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
 // Conductance from G = G_{1L} in Gbuf: X = G Phi_R -> Xbuf (n1 x P), then
 // S = Phi_L^T X in registers; returns T = sum_{p,q} d_p d_q |S_pq|^2 (every
 // thread). S is left in A (rows p, columns q) for callers that need it.
+// With chan set, the channel sums sum_q d_q |S_pq|^2 are left in
+// sm.rowacc[p] (the transmission of incoming channel p is d_p times that).
 template <int NW, int S, int C>
 __device__ __forceinline__ double trace_T(const SweepArgs& a, const Tuple& q,
                                           const cx<double>* Gbuf, cx<double>* Xbuf,
-                                          cx<double> (&A)[S][C], SweepSmem<NW, S, C>& sm) {
+                                          cx<double> (&A)[S][C], SweepSmem<NW, S, C>& sm,
+                                          bool chan = false) {
   constexpr int NP = NW * C;
   const int lane = lane_id(), w = wave_id();
   const int n1 = half_size(a.N, half_parity(0, a.parity));
@@ -393,6 +398,8 @@ __device__ __forceinline__ double trace_T(const SweepArgs& a, const Tuple& q,
     };
     gemm_regs<double, NW, S, C, KC>(A, nlast, fa, fb, sm.As, sm.Bs);
     store_regs<double, double, NW, S, C>(A, n1, a.P, Xbuf);
+    if (chan)
+      for (int i = threadIdx.x; i < NP; i += NW * 64) sm.rowacc[i] = 0.0;
     __syncthreads();
   }
   double part = 0.0;
@@ -408,15 +415,17 @@ __device__ __forceinline__ double trace_T(const SweepArgs& a, const Tuple& q,
     for (int s = 0; s < S; ++s) {
       const int p = lane + 64 * s;
       if (p >= a.P) continue;
-      const double dp = -2.0 * q.sig[p].im;
+      double row = 0.0;
 #pragma unroll
       for (int j = 0; j < C; ++j) {
         const int qq = w * C + j;
         if (qq < a.P) {
           const double dq = -2.0 * q.sig[qq].im;
-          part += dp * dq * (A[s][j].re * A[s][j].re + A[s][j].im * A[s][j].im);
+          row += dq * (A[s][j].re * A[s][j].re + A[s][j].im * A[s][j].im);
         }
       }
+      part += -2.0 * q.sig[p].im * row;
+      if (chan) atomicAdd(&sm.rowacc[p], row);
     }
   }
   return block_sum<NW>(part, sm.red);

@@ -273,6 +273,67 @@ def lead_self_energy(ribbon, energies, workspace=None):
     return torch.view_as_complex(sl), torch.view_as_complex(sr), st
 
 
+def channel_transmission(ribbon, energies, eps=None, n_real=1, precision="fp64",
+                         workspace=None, return_status=False):
+    """(T_channel [R, nE, P], T [R, nE]): the conductance split over the
+    incoming channels (transverse mode chains) of the left lead; the sum over
+    the last axis is T."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    if eps is not None:
+        if eps.dim() == 2:
+            eps = eps.unsqueeze(0)
+        _need(eps, "eps", (eps.shape[0], ribbon.L, ribbon.N))
+        n_real = eps.shape[0]
+    d = ribbon.desc()
+    L = _L.lib()
+    prec = _prec(precision)
+    P = ctypes.c_int32()
+    _L.check(L.rgf_lead_modes(ctypes.byref(d), None, 0, 0, None, None, ctypes.byref(P), None, 0,
+                              None))
+    nbytes = L.rgf_workspace_bytes(ctypes.byref(d), nE, int(n_real), prec, 0, 0)
+    if nbytes == 0:
+        msg = L.rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    ws = _workspace(workspace, nbytes, dev)
+    tc = torch.empty((int(n_real), nE, P.value), dtype=torch.float64, device=dev)
+    T = torch.empty((int(n_real), nE), dtype=torch.float64, device=dev)
+    st = torch.empty((int(n_real), nE), dtype=torch.int32, device=dev)
+    _L.check(L.rgf_channel_transmission(ctypes.byref(d), _vp(energies), nE, _vp(eps),
+                                        int(n_real), prec, _vp(tc), _vp(T), _vp(st), _vp(ws),
+                                        ws.numel(), _stream()))
+    if return_status:
+        return tc, T, st
+    return tc, T
+
+
+LEAD_METHODS = {"decimation": 0, "mode_matching": 1}
+
+
+def lead_modes(ribbon, energies, method="decimation", workspace=None):
+    """(sigma [nE, P] complex128, status [nE]): the per-mode lead
+    self-energies, by Sancho-Rubio decimation or by closed-form mode
+    matching."""
+    _need(energies, "energies")
+    if method not in LEAD_METHODS:
+        raise ValueError(f"method must be one of {sorted(LEAD_METHODS)}")
+    nE = energies.numel()
+    dev = energies.device
+    d = ribbon.desc()
+    L = _L.lib()
+    P = ctypes.c_int32()
+    _L.check(L.rgf_lead_modes(ctypes.byref(d), None, 0, 0, None, None, ctypes.byref(P), None, 0,
+                              None))
+    nbytes = L.rgf_workspace_bytes(ctypes.byref(d), nE, 1, 0, 0, 0)
+    ws = _workspace(workspace, nbytes, dev)
+    sig = torch.empty((nE, P.value, 2), dtype=torch.float64, device=dev)
+    st = torch.empty((nE,), dtype=torch.int32, device=dev)
+    _L.check(L.rgf_lead_modes(ctypes.byref(d), _vp(energies), nE, LEAD_METHODS[method], _vp(sig),
+                              _vp(st), None, _vp(ws), ws.numel(), _stream()))
+    return torch.view_as_complex(sig), st
+
+
 def autotune(ribbon, precision="fp64", device=None):
     """Time the register tilings for this width on the device and keep the
     fastest for later calls (process-wide). Returns (NW, S, C, slots_per_cu)."""

@@ -36,7 +36,7 @@ def test_version_and_strings():
     lib = L.lib()
     a, b = ctypes.c_int(), ctypes.c_int()
     assert lib.rgf_version(ctypes.byref(a), ctypes.byref(b)) == 0
-    assert (a.value, b.value) == (1, 1)
+    assert (a.value, b.value) == (1, 2)
     assert lib.rgf_status_string(-1) == b"RGF_ERR_INVALID_ARG"
     assert lib.rgf_status_string(-3) == b"RGF_ERR_WORKSPACE"
 
@@ -202,3 +202,27 @@ def test_wide_ribbon_workspace_scales_with_grid():
     slot = 21 * 128 * 128 * 16
     assert one >= slot + 2 * 240 * 256 * 8
     assert two - one >= slot
+
+
+def test_channel_transmission_and_lead_modes_arguments():
+    """rgf_channel_transmission runs in FP64 only; rgf_lead_modes reports the
+    number of modes P = ceil(N/2) with NULL outputs and rejects an unknown
+    method, all before anything is enqueued."""
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    d = L.make_desc(21, 5)
+    P = ctypes.c_int32()
+    assert lib.rgf_lead_modes(ctypes.byref(d), None, 0, 1, None, None, ctypes.byref(P), None,
+                              0, None) == 0
+    assert P.value == 11
+    assert lib.rgf_lead_modes(ctypes.byref(d), ctypes.c_void_p(16), 2, 2, ctypes.c_void_p(16),
+                              None, None, ctypes.c_void_p(256), 1 << 20, None) == -1
+    for prec in (1, 2):
+        rc = lib.rgf_channel_transmission(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, prec,
+                                          ctypes.c_void_p(16), ctypes.c_void_p(16), None,
+                                          ctypes.c_void_p(256), 1 << 30, None)
+        assert rc == L.RGF_ERR_UNSUPPORTED
+    rc = lib.rgf_channel_transmission(ctypes.byref(d), ctypes.c_void_p(16), 4, None, 1, 0,
+                                      None, ctypes.c_void_p(16), None, ctypes.c_void_p(256),
+                                      1 << 30, None)
+    assert rc == -1 and b"T_channel_out" in lib.rgf_last_error_message()
