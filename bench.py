@@ -617,7 +617,7 @@ def main():
     ev_mean_s = float(np.mean(r["ev_ms"])) / 1e3
     flops_call = flops_per_slice_step(N) * steps_per_call
     achieved = flops_call / ev_mean_s / 1e12
-    kname = "rgf_fwd_kernel<%s, %s, %d, %d, %d>" % (
+    kname = "rgf_fwd_kernel<%s, %s, %d, %d, %d, false>" % (
         "double" if prec == "fp64" else "float", "true" if prec == "mixed" else "false",
         *(r["tile"][:3] if r["tile"] else (0, 0, 0)))
     traffic = measured_traffic(kname)
