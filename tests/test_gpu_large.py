@@ -67,6 +67,21 @@ def test_wide_ribbons_match_oracle(P, row):
     assert abs(got[0, 0] - want) <= TOL_SMALL * max(1.0, abs(want)), (got[0, 0], want)
 
 
+@pytest.mark.parametrize("L,parity", [(1, 0), (2, 1)])
+def test_shortest_wide_ribbons(P, L, parity):
+    """L = 1 (both lead self-energies on the one slice) and L = 2 at
+    N = 258, against the oracle run here (its lead decimation at this width
+    takes seconds)."""
+    N = 258
+    E = -0.27 * abs(W.T_HOP)
+    eps = W.disorder(L, N, 0.5, r=30 + L)
+    _say("shortest wide", N, L, parity)
+    got, st = _gpu_T(P, N, L, parity, W.T_HOP, [E], eps[None])
+    assert st[0, 0] == 0
+    want = O.transmission(N, L, W.T_HOP, W.ETA, E, eps, parity)
+    assert abs(got[0, 0] - want) <= TOL_SMALL * max(1.0, abs(want)), (got[0, 0], want)
+
+
 def test_realizations_and_energies_in_one_launch(P):
     """Both N = 480 realizations and both stored energies in one call (one
     tuple per workgroup), against the same stored values."""
