@@ -160,6 +160,36 @@ def test_invariants_wide_disordered(P):
     assert np.abs(a - b).max() <= 1e-9
 
 
+def test_graph_capture_replays_wide(P):
+    """The N = 300 conductance call captured in a graph and replayed several
+    times, with eager work between replays, matches the eager result."""
+    import torch
+    N, L = 300, 4
+    _say("wide graph capture")
+    Es = torch.tensor(np.linspace(-0.3, 0.3, 6) * abs(W.T_HOP), device="cuda")
+    eps = torch.tensor(W.disorder_batch(L, N, 0.5, 2), device="cuda")
+    rib = P.Ribbon(N, L, 0, W.T_HOP, W.ETA)
+    ws = P.Workspace()
+    out = torch.empty((2, 6), dtype=torch.float64, device="cuda")
+    ref = P.conductance(rib, Es, eps, workspace=ws).clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        P.conductance(rib, Es, eps, workspace=ws, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.conductance(rib, Es, eps, workspace=ws, out=out)
+    for k in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+        P.conductance(rib, Es * 0.5, eps, workspace=ws)
+        torch.cuda.synchronize()
+
+
 def test_nan_energy_sets_status_wide(P):
     got, st = _gpu_T(P, 300, 3, 0, W.T_HOP, [0.3, float("nan")])
     assert st[0, 0] == 0 and np.isfinite(got[0, 0])
