@@ -568,6 +568,66 @@ def row_wide(args):
           flush=True)
 
 
+def row_wide_grad(args):
+    """Checkpointed gradient at the widest workload, large_n480 (N = 480,
+    L = 8000) at every 4th of its 1024 energies, FP64: one rgf_grad call
+    (weights 1/n_E: the gradient of the mean conductance). The restart states
+    take (2L/s + s) x 2 MB per workgroup with s = ceil(sqrt(2L)), about
+    133 GB for 256 workgroups."""
+    import torch
+
+    import paper_1107_5300_amd as P
+    cfg = W.WORKLOADS["large_n480"]
+    n, l = cfg["N"][0], cfg["L"]
+    Es = W.energies("large_n480")[::4]
+    eps = W.disorder(l, n, cfg["w"], r=0)
+    golden = np.atleast_2d(np.loadtxt(os.path.join(ROOT, "tests", "golden",
+                                                   "large_n480_sampled.txt")))
+    dev = torch.device("cuda:0")
+    rib = P.Ribbon(n, l, 0, W.T_HOP, W.ETA)
+    E = torch.tensor(Es, device=dev)
+    ep = torch.tensor(eps[None], device=dev)
+    w = torch.full((1, len(Es)), 1.0 / len(Es), dtype=torch.float64, device=dev)
+    ws = P.Workspace()
+    res = {}
+
+    def call():
+        res["T"], res["g"], res["st"] = P.grad(rib, E, ep, w, workspace=ws, return_status=True)
+        torch.cuda.synchronize()
+        _say("wide-grad: one call done")
+    wall, ev = _events(torch, call, args.steps, args.warmup)
+    T, g, st = (x.cpu().numpy()[0] for x in (res["T"], res["g"], res["st"]))
+    errs = {int(j): float(abs(T[int(j) // 4] - v)) for j, _, v in golden if int(j) % 4 == 0}
+    _say(f"wide-grad: {wall / args.steps:.1f} s per step, |dT| {errs}")
+    steps = len(Es) * l
+    ev_s = float(np.mean(ev)) / 1e3
+    fl = 3 * flops_per_slice_step(n) * steps
+    line = {
+        "metric": "checkpointed gradient, RGF slice-steps/s (forward + gradient) at N=480, FP64",
+        "value": steps * args.steps / wall, "unit": "slice-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "large_n480 (256 of 1024 energies), gradient of the mean T",
+                   "N": n, "L": l, "n_energies": len(Es), "n_real": 1, "precision": "fp64",
+                   "slice_steps_per_step": steps, "workspace_bytes": ws.buf.numel()},
+        "roofline": {"bound": "alu", "achieved": fl / ev_s / 1e12, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": fl / ev_s / 1e12 / PEAK_FP64_TFLOPS,
+                     "traffic": None, "kernel": "rgf_grad_large_kernel",
+                     "flops_per_slice_step": 3 * flops_per_slice_step(n),
+                     "event_ms_mean": ev_s * 1e3},
+        "cpu_baseline": None,
+        "accuracy": {"stored_oracle_energies": sorted(errs),
+                     "max_abs_dT_vs_oracle": max(errs.values()) if errs else None,
+                     "gradient": "checked against the oracle and finite differences at L <= 5 "
+                                 "(tests/test_gpu_large.py)",
+                     "tuples_not_ok": int((st != 0).sum()),
+                     "grad_finite": bool(np.isfinite(g).all())},
+    }
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -582,11 +642,12 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--row", default="main",
-                    choices=["main", "adjoint", "batched", "ldos", "wide"],
+                    choices=["main", "adjoint", "batched", "ldos", "wide", "wide-grad"],
                     help="main: the N=240 sweep (the metric); adjoint: gradient sweep of the "
                          "N=120 workload; batched: the mixed-width batched launch; ldos: "
                          "local density of states of the N=120 workload; wide: the N=480 "
-                         "workload through the blocked half-slice inversion")
+                         "workload through the blocked half-slice inversion; wide-grad: its "
+                         "checkpointed gradient")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -601,6 +662,8 @@ def main():
         return row_ldos(args)
     if args.row == "wide":
         return row_wide(args)
+    if args.row == "wide-grad":
+        return row_wide_grad(args)
 
     Es = W.energies(WORKLOAD)
     eps = W.disorder(L, N, WDIS, r=0)
