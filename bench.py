@@ -162,10 +162,10 @@ def csrc_fingerprint():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name):
-    """HBM-side bytes per launch from the committed counter summary, or None
-    when it was taken on another kernel or on other sources."""
-    path = os.path.join(ROOT, "profiles", "rgf_fwd_kernel_disorder_n240_traffic.md")
+def _profile_record(name, kernel_name):
+    """The machine-readable line of a committed counter summary, or None when
+    it was taken on another kernel or on other sources."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as fh:
             line = [ln for ln in fh if ln.startswith("machine-readable: ")][-1]
@@ -174,7 +174,19 @@ def measured_traffic(kernel_name):
         return None
     if rec.get("kernel") != kernel_name or rec.get("csrc_fingerprint") != csrc_fingerprint():
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    return rec
+
+
+def measured_traffic(kernel_name):
+    """HBM-side bytes per launch from the committed counter summary, or None."""
+    rec = _profile_record("rgf_fwd_kernel_disorder_n240_traffic.md", kernel_name)
+    return None if rec is None else float(rec["traffic_bytes_per_launch"])
+
+
+def measured_issued(kernel_name):
+    """Issued FP64 flops per launch (vector ALUs + matrix cores) and the
+    matrix cores' busy fraction from the committed counter summary, or None."""
+    return _profile_record("rgf_fwd_kernel_disorder_n240_flops.md", kernel_name)
 
 
 def copy_calibration(nbytes=1 << 28):
@@ -708,6 +720,7 @@ def main():
         "double" if prec == "fp64" else "float", "true" if prec == "mixed" else "false",
         *(r["tile"][:3] if r["tile"] else (0, 0, 0)))
     traffic = measured_traffic(kname)
+    issued = measured_issued(kname)
     line = {
         "metric": METRIC,
         "value": value,
@@ -739,6 +752,12 @@ def main():
             "tile": r["tile"],
             "flops_per_slice_step": flops_per_slice_step(N),
             "dense_equiv_tflops": dense_equiv_flops(N) * steps_per_call / ev_mean_s / 1e12,
+            "issued_frac": None if issued is None else
+            issued["issued_fp64_flops_per_launch"] / ev_mean_s / 1e12 / PEAK_FP64_TFLOPS,
+            "mfma_busy_frac": None if issued is None else issued["mfma_busy_fraction"],
+            "issued_note": "FP64 flops issued on the vector ALUs and matrix cores (rocprofv3 "
+                           "counters, profiles/rgf_fwd_kernel_disorder_n240_flops.md) over the "
+                           "event time; null when the sources differ from the counted ones",
             "event_ms_mean": ev_mean_s * 1e3,
         },
         "recursion_only": {
