@@ -226,3 +226,15 @@ def test_channel_transmission_and_lead_modes_arguments():
                                       None, ctypes.c_void_p(16), None, ctypes.c_void_p(256),
                                       1 << 30, None)
     assert rc == -1 and b"T_channel_out" in lib.rgf_last_error_message()
+
+
+def test_autotune_wide_widths():
+    """Above N = 256 the autotuner has one configuration: FP64 needs no tuning
+    workspace beyond the trial buffers, and FP32 modes are rejected."""
+    from paper_1107_5300_amd import _lib as L
+    lib = L.lib()
+    d = L.make_desc(480, 8)
+    assert lib.rgf_autotune_workspace_bytes(ctypes.byref(d), 0) > 0
+    for prec in (1, 2):
+        assert lib.rgf_autotune_workspace_bytes(ctypes.byref(d), prec) == 0
+        assert b"FP64 only" in lib.rgf_last_error_message()
