@@ -435,9 +435,15 @@ def row_batched(args):
     widths, l, nreal = (60, 120, 240), 1000, 16
     Es = W.energies("batched_mixed")[::16]
     epss = [W.disorder_batch(l, n, 0.5, nreal) for n in widths]
+    # 64 seeded (width, realization, energy) tuples for the oracle, half of
+    # them near the charge-neutrality point (|E| < 0.05|t|)
     rng = np.random.default_rng(7)
-    checks = [(d, int(rng.integers(nreal)), int(rng.integers(len(Es)))) for d in range(3)
-              for _ in range(4)]
+    near = np.flatnonzero(np.abs(Es) < 0.05 * abs(W.T_HOP))
+    far = np.flatnonzero(np.abs(Es) >= 0.05 * abs(W.T_HOP))
+    checks = []
+    for i in range(64):
+        pool = near if i % 2 == 0 else far
+        checks.append((i % 3, int(rng.integers(nreal)), int(pool[rng.integers(len(pool))])))
     cpu = None
     if not args.no_cpu:
         jobs = [(widths[d], l, Es[e], epss[d][r]) for d, r, e in checks]
@@ -445,8 +451,8 @@ def row_batched(args):
         _say(f"batched: oracle sample done in {wall_c:.1f} s")
         steps_c = len(jobs) * l
         cpu = {"value": steps_c / wall_c, "unit": "slice-steps/s", "cores": nw, "kind": "oracle",
-               "sample": f"{len(jobs)} (width, realization, energy) tuples, 4 per width, at full "
-                         f"length, one per process; {wall_c:.1f} s wall"}
+               "sample": f"{len(jobs)} seeded (width, realization, energy) tuples, half with "
+                         f"|E| < 0.05|t|, at full length, one per process; {wall_c:.1f} s wall"}
     else:
         want = None
     dev = torch.device("cuda:0")
