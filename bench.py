@@ -538,7 +538,9 @@ def row_wide(args):
         jobs = [(n, ls, Es[j], eps) for j in np.linspace(0, len(Es) - 1, 16).round().astype(int)]
         per, wall_c, nw = _pool_map(_oracle_sweep_timing_job, jobs)
         cpu = {"value": len(jobs) * ls / wall_c, "unit": "slice-steps/s", "cores": nw,
-               "kind": "oracle",
+               "kind": "oracle", "single_core_value": ls / float(np.mean(per)),
+               "full_workload_s_extrapolated":
+                   len(W.energies("large_n480")) * l / (len(jobs) * ls / wall_c),
                "sample": f"{len(jobs)} energies x the first {ls} slices of the N={n} ribbon, "
                          f"oracle recursion only (lead self-energies set to zero, timing only), "
                          f"one energy per process; {wall_c:.1f} s wall"}
