@@ -670,9 +670,9 @@ def main():
                          "checkpointed gradient")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(tuples would shard across GPUs with one gather of T; see DESIGN.md)",
-              file=sys.stderr)
+        print(f"bench.py: the benchmark measures one GPU; --gpus {args.gpus} is not supported "
+              "(the (width, realization, energy) tuples are independent and would shard across "
+              "GPUs with one gather of T)", file=sys.stderr)
         sys.exit(2)
     if args.row == "adjoint":
         return row_adjoint(args)
