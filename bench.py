@@ -427,13 +427,16 @@ def row_ldos(args):
 
 def row_batched(args):
     """Mixed-width batched launch, workload batched_mixed at every 16th of its
-    4096 energies (256, 32 of them in |E| < 0.05|t|): widths 60, 120, 240,
-    L = 1000, 16 realizations, one rgf_conductance_batched call."""
+    4096 energies (256, 32 of them in |E| < 0.05|t|), or all of them with
+    --full (FP64 only): widths 60, 120, 240, L = 1000, 16 realizations, one
+    rgf_conductance_batched call."""
     import torch
 
     import paper_1107_5300_amd as P
     widths, l, nreal = (60, 120, 240), 1000, 16
-    Es = W.energies("batched_mixed")[::16]
+    Es = W.energies("batched_mixed")
+    if not args.full:
+        Es = Es[::16]
     epss = [W.disorder_batch(l, n, 0.5, nreal) for n in widths]
     # 64 seeded (width, realization, energy) tuples for the oracle, half of
     # them near the charge-neutrality point (|E| < 0.05|t|)
@@ -460,21 +463,27 @@ def row_batched(args):
     E = torch.tensor(Es, device=dev)
     eps_d = [torch.tensor(e, device=dev) for e in epss]
     out = {}
-    for prec in ("fp64", "mixed"):
+    for prec in (("fp64",) if args.full else ("fp64", "mixed")):
         tiles = [P.autotune(rb, prec) for rb in ribs]
         ws = P.Workspace()
         res = {}
 
         def call():
             res["T"] = P.conductance_batched(ribs, E, eps_d, precision=prec, workspace=ws)
+            if args.full:   # minutes per call: report each
+                torch.cuda.synchronize()
+                _say("batched: one call done")
         wall, ev = _events(torch, call, args.steps, args.warmup)
         Ts = [t.cpu().numpy() for t in res["T"]]
         err = None if want is None else max(abs(Ts[d][r, e] - v) for (d, r, e), v in
                                              zip(checks, want))
         out[prec] = dict(wall=wall, ev=ev, err=err, tiles=tiles, T=Ts)
         _say(f"batched {prec}: {wall / args.steps:.3f} s per step")
-    dmix = max(float(np.abs(a - b).max()) for a, b in zip(out["mixed"]["T"], out["fp64"]["T"]))
-    out["mixed"]["vs64"], out["fp64"]["vs64"] = dmix, 0.0
+    dmix = None
+    if "mixed" in out:
+        dmix = max(float(np.abs(a - b).max()) for a, b in zip(out["mixed"]["T"], out["fp64"]["T"]))
+        out["mixed"]["vs64"] = dmix
+    out["fp64"]["vs64"] = 0.0
     ok = [p for p in out if (out[p]["err"] if out[p]["err"] is not None else out[p]["vs64"])
           <= ACC_TOL] or list(out)
     prec = min(ok, key=lambda p: out[p]["wall"])
@@ -488,7 +497,8 @@ def row_batched(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall"] / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "mixed": "f32+f64"}[prec], "data": "synthetic",
-        "config": {"workload": "batched_mixed (256 of 4096 energies)", "N": list(widths), "L": l,
+        "config": {"workload": "batched_mixed" + ("" if args.full else " (256 of 4096 energies)"),
+                   "N": list(widths), "L": l,
                    "n_energies": len(Es), "n_real": nreal, "precision": prec,
                    "slice_steps_per_step": steps},
         "roofline": {"bound": "alu", "achieved": flops / ev_s / 1e12, "peak": PEAK_FP64_TFLOPS,
@@ -659,6 +669,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle legs (baseline and accuracy samples)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--full", action="store_true",
+                    help="--row batched: all 4096 energies of the workload, FP64 only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--row", default="main",
