@@ -538,7 +538,8 @@ def row_wide(args):
     import paper_1107_5300_amd as P
     cfg = W.WORKLOADS["large_n480"]
     n, l = cfg["N"][0], cfg["L"]
-    Es = W.energies("large_n480")[::4]
+    stride = 1 if args.full else 4
+    Es = W.energies("large_n480")[::stride]
     eps = W.disorder(l, n, cfg["w"], r=0)
     golden = np.atleast_2d(np.loadtxt(os.path.join(ROOT, "tests", "golden",
                                                    "large_n480_sampled.txt")))
@@ -563,14 +564,19 @@ def row_wide(args):
     res = {}
 
     def call():
-        res["T"] = P.conductance(rib, E, ep, workspace=ws)
-        torch.cuda.synchronize()   # one call takes tens of seconds: report each
-        _say("wide: one call done")
+        # chunks of 256 energies (one tuple per compute unit), tens of
+        # seconds each: report each
+        outs = []
+        for c0 in range(0, len(Es), 256):
+            outs.append(P.conductance(rib, E[c0:c0 + 256], ep, workspace=ws, return_status=True))
+            torch.cuda.synchronize()
+            _say("wide: one chunk done")
+        res["T"] = torch.cat([o[0] for o in outs], dim=1)
+        res["st"] = torch.cat([o[1] for o in outs], dim=1)
     wall, ev = _events(torch, call, args.steps, args.warmup)
-    T, st = P.conductance(rib, E, ep, workspace=ws, return_status=True)
-    torch.cuda.synchronize()
-    T, st = T.cpu().numpy()[0], st.cpu().numpy()[0]
-    errs = {int(j): float(abs(T[int(j) // 4] - v)) for j, _, v in golden if int(j) % 4 == 0}
+    T, st = res["T"].cpu().numpy()[0], res["st"].cpu().numpy()[0]
+    errs = {int(j): float(abs(T[int(j) // stride] - v)) for j, _, v in golden
+            if int(j) % stride == 0}
     _say(f"wide: {wall / args.steps:.2f} s per step, |dT| {errs}")
     steps = len(Es) * l
     ev_s = float(np.mean(ev)) / 1e3
@@ -581,7 +587,8 @@ def row_wide(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "large_n480 (256 of 1024 energies)", "N": n, "L": l,
+        "config": {"workload": "large_n480" + ("" if args.full else " (256 of 1024 energies)"),
+                   "N": n, "L": l,
                    "n_energies": len(Es), "n_real": 1, "precision": "fp64",
                    "slice_steps_per_step": steps},
         "roofline": {"bound": "alu", "achieved": fl / ev_s / 1e12, "peak": PEAK_FP64_TFLOPS,
@@ -609,7 +616,8 @@ def row_wide_grad(args):
     import paper_1107_5300_amd as P
     cfg = W.WORKLOADS["large_n480"]
     n, l = cfg["N"][0], cfg["L"]
-    Es = W.energies("large_n480")[::4]
+    stride = 1 if args.full else 4
+    Es = W.energies("large_n480")[::stride]
     eps = W.disorder(l, n, cfg["w"], r=0)
     golden = np.atleast_2d(np.loadtxt(os.path.join(ROOT, "tests", "golden",
                                                    "large_n480_sampled.txt")))
@@ -622,12 +630,21 @@ def row_wide_grad(args):
     res = {}
 
     def call():
-        res["T"], res["g"], res["st"] = P.grad(rib, E, ep, w, workspace=ws, return_status=True)
-        torch.cuda.synchronize()
-        _say("wide-grad: one call done")
+        # chunks of 256 energies (one tuple per compute unit), about two
+        # minutes each: report each; the gradients of the chunks add up
+        outs = []
+        for c0 in range(0, len(Es), 256):
+            outs.append(P.grad(rib, E[c0:c0 + 256], ep, w[:, c0:c0 + 256].contiguous(),
+                               workspace=ws, return_status=True))
+            torch.cuda.synchronize()
+            _say("wide-grad: one chunk done")
+        res["T"] = torch.cat([o[0] for o in outs], dim=1)
+        res["g"] = sum(o[1] for o in outs)
+        res["st"] = torch.cat([o[2] for o in outs], dim=1)
     wall, ev = _events(torch, call, args.steps, args.warmup)
     T, g, st = (x.cpu().numpy()[0] for x in (res["T"], res["g"], res["st"]))
-    errs = {int(j): float(abs(T[int(j) // 4] - v)) for j, _, v in golden if int(j) % 4 == 0}
+    errs = {int(j): float(abs(T[int(j) // stride] - v)) for j, _, v in golden
+            if int(j) % stride == 0}
     _say(f"wide-grad: {wall / args.steps:.1f} s per step, |dT| {errs}")
     steps = len(Es) * l
     ev_s = float(np.mean(ev)) / 1e3
@@ -638,7 +655,8 @@ def row_wide_grad(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "large_n480 (256 of 1024 energies), gradient of the mean T",
+        "config": {"workload": "large_n480" + ("" if args.full else " (256 of 1024 energies)")
+                   + ", gradient of the mean T",
                    "N": n, "L": l, "n_energies": len(Es), "n_real": 1, "precision": "fp64",
                    "slice_steps_per_step": steps, "workspace_bytes": ws.buf.numel()},
         "roofline": {"bound": "alu", "achieved": fl / ev_s / 1e12, "peak": PEAK_FP64_TFLOPS,
@@ -670,7 +688,8 @@ def main():
                     help="skip the CPU oracle legs (baseline and accuracy samples)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--full", action="store_true",
-                    help="--row batched: all 4096 energies of the workload, FP64 only")
+                    help="--row batched / wide / wide-grad: every energy of the workload "
+                         "(batched: FP64 only)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--row", default="main",
