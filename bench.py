@@ -61,6 +61,26 @@ def _oracle_job(args):
     return j, T, time.perf_counter() - t0
 
 
+def host_description():
+    """CPU model and BLAS library of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                         None)
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [f"{i.get('internal_api')} {i.get('version')}" for i in threadpool_info()
+                if i.get("user_api") == "blas"]
+        blas = ", ".join(libs) or None
+    except Exception:   # threadpoolctl missing or unable to inspect: leave it unnamed
+        pass
+    return model, blas
+
+
 def cpu_baseline(Es, eps, max_workers=16):
     import multiprocessing as mp
     cores = len(os.sched_getaffinity(0))
@@ -808,7 +828,8 @@ def main():
         "cpu_baseline": None if cpu is None else dict(
             {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
             single_core_value=L / cpu["per_energy_s"],
-            full_workload_s_extrapolated=len(Es) * L / cpu["value"]),
+            full_workload_s_extrapolated=len(Es) * L / cpu["value"],
+            cpu_model=host_description()[0], blas=host_description()[1]),
         "accuracy": {
             "max_abs_dT_vs_oracle": None if r["dT"] is None else float(r["dT"]),
             "oracle_energies": sorted(oracle_T.keys()),
