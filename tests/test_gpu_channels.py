@@ -157,6 +157,21 @@ def test_channels_wide_pristine_and_sum(P):
     assert ((tc >= -1e-12) & (tc <= 1 + 1e-9)).all()
 
 
+def test_channels_wide_vs_oracle(P):
+    """N = 258 (panel path), L = 2, disordered: the channel list against the
+    oracle's eigen-decomposition of its dense Gamma_L, run here (its lead
+    decimation at this width takes seconds)."""
+    N, L = 258, 2
+    eps = W.disorder(L, N, 0.5, r=58)
+    E = 0.31 * abs(W.T_HOP)
+    _say("channels wide oracle", N, L)
+    tc, T, st = _chan(P, N, L, 1, W.T_HOP, [E], eps[None])
+    assert st[0, 0] == 0
+    _, ti = O.channel_transmission(N, L, W.T_HOP, W.ETA, E, eps, 1, rel_tol=1e-14)
+    _compare(tc[0, 0], ti)
+    assert abs(tc[0, 0].sum() - T[0, 0]) <= 1e-12 * max(1.0, T[0, 0])
+
+
 def test_channels_nan_status(P):
     tc, T, st = _chan(P, 10, 5, 0, W.T_HOP, [0.3, float("nan")])
     assert st[0, 0] == 0 and st[0, 1] != 0
