@@ -23,7 +23,8 @@
  *     never cross the boundary, except the debug export of the lead
  *     self-energies, which is interleaved (re, im) float64), in row-major
  *     C order, owned by the caller. The library allocates no device memory on
- *     any path: scratch space is the caller's workspace.
+ *     any path: scratch space is the caller's workspace (for
+ *     rgf_conductance_noalloc, a fixed device array inside the library).
  *   - Calls are asynchronous on the caller's HIP stream (hipStream_t passed as
  *     void*; NULL = the null stream). The return value reports only errors
  *     found before anything is enqueued (invalid arguments, an undersized
@@ -189,6 +190,26 @@ int rgf_conductance_batched(const rgf_ribbon_desc* descs, int32_t n_desc,
                             int precision, double* T_out, int32_t* status_out,
                             void* workspace, size_t workspace_bytes,
                             void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and kernels as rgf_conductance, with no workspace argument.
+ * Scratch comes from a fixed device array inside librgf of
+ * RGF_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that GPU
+ * until the process ends; the call allocates nothing. When the normal plan
+ * does not fit, fewer persistent workgroups run (same results, lower
+ * throughput); a call whose lead tables plus one workgroup slot exceed the
+ * array returns RGF_ERR_WORKSPACE before anything is enqueued. Nothing in
+ * the array must start at zero. Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (different streams, or several
+ * host threads) race and must be serialised by the caller. The first call
+ * on a device resolves the array's device address (not a stream operation);
+ * make it outside stream capture. Arguments as for rgf_conductance. */
+#define RGF_NOALLOC_SCRATCH_BYTES ((size_t)192 << 20)
+int rgf_conductance_noalloc(const rgf_ribbon_desc* desc, const double* energies_ev,
+                            int64_t n_energies, const double* onsite_eps_ev,
+                            int64_t n_real, int precision, double* T_out,
+                            int32_t* status_out, void* hip_stream);
 
 /* Lead self-energies (method section; Sancho-Rubio decimation in FP64),
  * restricted to the rows that bond to the device:

@@ -11,6 +11,7 @@ from .rgf import (  # noqa: F401
     Workspace,
     conductance,
     conductance_batched,
+    conductance_noalloc,
     grad,
     ldos,
     RGFConductance,

@@ -38,6 +38,7 @@ EXPORTED = (
     "rgf_lead_modes",
     "rgf_batched_workspace_bytes",
     "rgf_conductance_batched",
+    "rgf_conductance_noalloc",
     "rgf_lead_self_energy",
     "rgf_autotune_workspace_bytes",
     "rgf_autotune",
@@ -96,6 +97,8 @@ def _declare(lib):
     lib.rgf_conductance_batched.restype = _int
     lib.rgf_conductance_batched.argtypes = [_pdesc, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _int,
                                             _vp, _vp, _vp, _sz, _vp]
+    lib.rgf_conductance_noalloc.restype = _int
+    lib.rgf_conductance_noalloc.argtypes = [_pdesc, _vp, _i64, _vp, _i64, _int, _vp, _vp, _vp]
     lib.rgf_lead_self_energy.restype = _int
     lib.rgf_lead_self_energy.argtypes = [_pdesc, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                          _vp]

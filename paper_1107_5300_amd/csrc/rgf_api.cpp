@@ -64,7 +64,7 @@ static int validate_desc(const rgf_ribbon_desc* d) {
 }
 
 int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision,
-              int want_grad, int64_t ckpt_stride, Plan* p) {
+              int want_grad, int64_t ckpt_stride, Plan* p, int grid_cap) {
   int st = validate_desc(d);
   if (st != RGF_OK) return st;
   if (nE < 0) return fail(RGF_ERR_INVALID_ARG, "n_energies = %lld < 0", (long long)nE);
@@ -131,6 +131,7 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
     q.mat_elems = q.slot_elems;
     q.phi_ld = NP;
   }
+  if (grid_cap > 0 && q.grid > grid_cap) q.grid = grid_cap;
   size_t off = 0;
   q.off_sigma = off;
   off = align_up(off + (size_t)nE * q.P * 16, 256);

@@ -64,8 +64,9 @@ struct Plan {
 };
 
 // Fill the plan; returns RGF_OK or an error code (with message set).
+// grid_cap > 0 limits the persistent grid (fewer slots, a smaller workspace).
 int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision,
-              int want_grad, int64_t ckpt_stride, Plan* p);
+              int want_grad, int64_t ckpt_stride, Plan* p, int grid_cap = 0);
 
 void set_error(const char* fmt, ...);
 

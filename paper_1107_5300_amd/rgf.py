@@ -119,6 +119,33 @@ def conductance(ribbon, energies, eps=None, n_real=1, precision="fp64", workspac
     return T
 
 
+def conductance_noalloc(ribbon, energies, eps=None, n_real=1, precision="fp64",
+                        return_status=False, out=None, status_out=None):
+    """The conductance of `conductance`, computed in the library's fixed
+    device scratch instead of a torch workspace (no allocation inside the
+    library call; pass `out` and `status_out` to allocate nothing at all).
+    Calls that overlap on one GPU share that scratch and must not run
+    concurrently."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    if eps is not None:
+        if eps.dim() == 2:
+            eps = eps.unsqueeze(0)
+        _need(eps, "eps", (eps.shape[0], ribbon.L, ribbon.N))
+        n_real = eps.shape[0]
+    d = ribbon.desc()
+    T = out if out is not None else torch.empty((int(n_real), nE), dtype=torch.float64, device=dev)
+    st = status_out if status_out is not None else torch.empty((int(n_real), nE),
+                                                               dtype=torch.int32, device=dev)
+    _L.check(_L.lib().rgf_conductance_noalloc(ctypes.byref(d), _vp(energies), nE, _vp(eps),
+                                              int(n_real), _prec(precision), _vp(T), _vp(st),
+                                              _stream()))
+    if return_status:
+        return T, st
+    return T
+
+
 def conductance_batched(ribbons, energies, eps_list=None, n_real=1, precision="fp64",
                         workspace=None, return_status=False):
     """Several ribbons (e.g. mixed widths) sharing one energy grid and one
