@@ -94,12 +94,24 @@ enum {
   RGF_TUPLE_NO_CONVERGENCE = 1, /* lead decimation hit its iteration cap     */
   RGF_TUPLE_SINGULAR = 2,       /* exact zero pivot in a slice inversion     */
   RGF_TUPLE_NONFINITE = 3,      /* T came out NaN or Inf                     */
-  RGF_TUPLE_OUT_OF_RANGE = 4    /* T outside [0, number of lead modes]: the
-                                   recursion lost its accuracy. Seen at E = 0
-                                   exactly when on-site energies vanish: each
-                                   half-slice is then one sublattice with no
-                                   diagonal term, and its left-connected
-                                   Green's function grows like 1/eta      */
+  RGF_TUPLE_OUT_OF_RANGE = 4,   /* T outside [0, number of lead modes]: the
+                                   recursion lost its accuracy             */
+  RGF_TUPLE_ILL_CONDITIONED = 5 /* the half-slice recursion (each slice
+                                   inverted as its two row classes) is too
+                                   ill-conditioned for this tuple: its
+                                   summed condition estimates say the
+                                   rounding error of T could pass ~1e-9.
+                                   Happens for pristine or nearly pristine
+                                   ribbons within ~1e-3 eV of E = 0, where
+                                   cutting a slice between its row classes
+                                   leaves zero-energy dangling-bond states.
+                                   rgf_conductance, rgf_conductance_noalloc,
+                                   rgf_conductance_batched and
+                                   rgf_channel_transmission (FP64 and
+                                   mixed) then recompute the tuple with
+                                   whole N x N slice inversions and never
+                                   return this code; rgf_grad and rgf_ldos
+                                   report it with NaN outputs             */
 };
 
 /* Bytes of device workspace the call with the same arguments needs.

@@ -27,6 +27,7 @@ TUPLE_NO_CONVERGENCE = 1
 TUPLE_SINGULAR = 2
 TUPLE_NONFINITE = 3
 TUPLE_OUT_OF_RANGE = 4
+TUPLE_ILL_CONDITIONED = 5
 
 # every symbol declared in include/rgf.h
 EXPORTED = (

@@ -139,9 +139,22 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   off = align_up(off + (size_t)2 * q.P * q.phi_ld * 8, 256);
   q.off_lstat = off;
   off = align_up(off + (size_t)nE * 4, 256);
+  const bool fallback = !q.want_grad && precision != RGF_PREC_FP32;
+  q.off_flags = off;
+  if (fallback) off = align_up(off + (size_t)q.ntuples * 4, 256);
   q.off_status = off;
   q.off_slots = off;
-  off = align_up(off + (size_t)q.grid * q.slot_mats * q.slot_elems * 16, 256);
+  const size_t slots_bytes = (size_t)q.grid * q.slot_mats * q.slot_elems * 16;
+  off = align_up(off + slots_bytes, 256);
+  if (fallback) {
+    // the whole-slice workgroups reuse the slot region after the sweep; at
+    // least one of them fits
+    const size_t fb_slot = whole_slot_bytes(q.N);
+    int64_t g = (int64_t)(slots_bytes / fb_slot);
+    g = std::min<int64_t>(g, std::min<int64_t>(std::max<int64_t>(q.ntuples, 1), device_cu_count()));
+    q.fb_grid = (int)std::max<int64_t>(g, 1);
+    off = std::max(off, align_up(q.off_slots + (size_t)q.fb_grid * fb_slot, 256));
+  }
   q.off_ckpt = q.off_seg = off;
   if (q.want_grad) {
     const int64_t H = 2 * (int64_t)q.L;
@@ -182,30 +195,61 @@ void set_tuned_choice(int n, int precision, int tile_id, int per_cu) {
   g_tuned[{n, precision}] = {tile_id, per_cu};
 }
 
+// Device properties and kernel occupancies are queried once per device
+// (plans are made on every call, twice per torch call).
+namespace {
+struct DeviceInfo {
+  int ncu = 0;
+  std::map<std::pair<const void*, int>, int> occupancy;  // (kernel, threads) -> blocks per CU
+};
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_dev;
+
+bool current_device(int* dev) {
+  if (hipGetDevice(dev) == hipSuccess) return true;
+  (void)hipGetLastError();
+  return false;
+}
+
+// Blocks of `threads` threads of kernel k per CU on the current device (1 if
+// unknown).
+int kernel_occupancy(const void* k, int threads) {
+  int dev = 0;
+  if (!k || !current_device(&dev)) return 1;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto& m = g_dev[dev].occupancy;
+  auto it = m.find({k, threads});
+  if (it != m.end()) return it->second;
+  int o = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, threads, 0) != hipSuccess || o < 1) {
+    (void)hipGetLastError();
+    return 1;  // not cached: a later call may succeed
+  }
+  m[{k, threads}] = o;
+  return o;
+}
+}  // namespace
+
 int device_cu_count() {
   int dev = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    return prop.multiProcessorCount;
-  (void)hipGetLastError();
-  return 256;
+  if (!current_device(&dev)) return 256;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DeviceInfo& d = g_dev[dev];
+  if (d.ncu == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return 256;
+    }
+    d.ncu = prop.multiProcessorCount;
+  }
+  return d.ncu;
 }
 
 int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad, int per_cu) {
-  int dev = 0, ncu = 256, occ = 1;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-    const void* k = grad ? grad_kernel_ptr(t, precision) : fwd_kernel_ptr(t, precision);
-    int o = 0;
-    if (k && hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, t.threads(), 0) == hipSuccess &&
-        o > 0)
-      occ = o;
-    else
-      (void)hipGetLastError();
-  } else {
-    (void)hipGetLastError();
-  }
+  const int ncu = device_cu_count();
+  const void* k = grad ? grad_kernel_ptr(t, precision) : fwd_kernel_ptr(t, precision);
+  int occ = kernel_occupancy(k, t.threads());
   if (per_cu > 0 && per_cu < occ) occ = per_cu;
   int64_t g = (int64_t)ncu * occ;
   if (g > ntuples) g = ntuples;
@@ -214,21 +258,8 @@ int persistent_grid(const TileCfg& t, int64_t ntuples, int precision, bool grad,
 }
 
 int persistent_grid_large(int64_t ntuples, bool grad) {
-  int dev = 0, ncu = 256, occ = 1;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-    int o = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, large_kernel_ptr(grad),
-                                                     large_block_tile().threads(), 0) ==
-            hipSuccess &&
-        o > 0)
-      occ = o;
-    else
-      (void)hipGetLastError();
-  } else {
-    (void)hipGetLastError();
-  }
+  const int ncu = device_cu_count();
+  const int occ = kernel_occupancy(large_kernel_ptr(grad), large_block_tile().threads());
   int64_t g = (int64_t)ncu * occ;
   if (g > ntuples) g = ntuples;
   if (g < 1) g = 1;
@@ -452,13 +483,7 @@ int tune_plan(const rgf_ribbon_desc* desc, int precision, rgf_ribbon_desc* dd,
   if (st != RGF_OK) return st;
   *dd = *desc;
   dd->length_l = std::min(desc->length_l, kTuneL);
-  int dev = 0, ncu = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    ncu = prop.multiProcessorCount;
-  else
-    (void)hipGetLastError();
-  ts->nE = (int64_t)ncu * 4;  // enough tuples for every grid size tried
+  ts->nE = (int64_t)device_cu_count() * 4;  // enough tuples for every grid size tried
   if ((desc->width_n + 1) / 2 > kTileMaxRows && precision != RGF_PREC_FP64)
     return fail(RGF_ERR_UNSUPPORTED, "width_n = %d: half-slices above %d rows run in FP64 only",
                 desc->width_n, kTileMaxRows);
@@ -476,9 +501,12 @@ size_t tune_bytes_for(const rgf_ribbon_desc* dd, int64_t nE, int precision) {
     const TileCfg t = tile_at(i);
     if (t.NP() < n || 64 * t.S < t.NP()) continue;
     const size_t NP = (size_t)t.NP();
+    const bool fallback = precision != RGF_PREC_FP32;  // flags + whole-slice slots
     const size_t head = align_up((size_t)nE * P * 16, 256) + align_up(2 * (size_t)P * NP * 8, 256) +
-                        align_up((size_t)nE * 4, 256);
-    const size_t slots = (size_t)persistent_grid(t, nE, precision, false) * mats * NP * NP * 16;
+                        align_up((size_t)nE * 4, 256) +
+                        (fallback ? align_up((size_t)nE * 4, 256) : 0);
+    size_t slots = (size_t)persistent_grid(t, nE, precision, false) * mats * NP * NP * 16;
+    if (fallback) slots = std::max(slots, whole_slot_bytes(dd->width_n));
     mx = std::max(mx, head + align_up(slots, 256));
   }
   return align_up((size_t)nE * 16, 256) + mx;

@@ -26,6 +26,8 @@ template <typename TJ, bool REFINE, int NW, int S, int C, bool CHAN = false>
 __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_fwd_kernel(
     SweepArgs a) {
   constexpr int NP = NW * C;
+  // the accuracy guard covers the FP64 and mixed modes (not the FP32 study)
+  constexpr bool GUARD = sizeof(TJ) == sizeof(double) || REFINE;
   __shared__ SweepSmem<NW, S, C> sm;
   cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * NP * NP;
   cx<double>* kb[2] = {slot, REFINE ? slot + (size_t)3 * NP * NP : slot};
@@ -34,7 +36,11 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_f
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
-    if (threadIdx.x == 0) sm.flag = 0;
+    if (threadIdx.x == 0) {
+      sm.flag = 0;
+      sm.ksum = 0.0;
+      sm.ksum_c = 0.0;
+    }
     __syncthreads();
     cx<double> A[S][C];
     for (int h = 0; h < 2 * a.L; ++h) {
@@ -44,12 +50,18 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_f
     const double T = trace_T<NW, S, C>(a, q, gbuf, rbuf, A, sm, CHAN);
     if (CHAN || threadIdx.x == 0) {
       int st = a.lstat[q.e];
+      // the guard first: a rejected sweep may also show a zero pivot or a T
+      // out of range, and the whole-slice sweep recomputes it
+      if (GUARD && st == RGF_TUPLE_OK && ill_conditioned(sm.ksum, sm.ksum_c))
+        st = RGF_TUPLE_ILL_CONDITIONED;
       if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
       if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
       if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
       if (threadIdx.x == 0) {
         a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
         if (a.status) a.status[tau] = st;
+        // the whole-slice sweep recomputes the tuples the guard rejected
+        if (a.fb_flags) a.fb_flags[tau] = (st == RGF_TUPLE_ILL_CONDITIONED) ? 1 : 0;
       }
       if constexpr (CHAN) {  // T_p = d_p sum_q d_q |S_pq|^2 (block_sum's barriers order rowacc)
         for (int p = threadIdx.x; p < a.P; p += NW * 64)
@@ -144,10 +156,14 @@ hipError_t launch_forward(const Plan& p, const double* E, const double* eps, dou
   a.slot_mats = p.slot_mats;
   a.ntuples = p.ntuples;
   a.tchan = tchan;
+  a.phi_ld = p.phi_ld;
+  a.fb_flags = p.fb_grid > 0 ? reinterpret_cast<int32_t*>(ws + p.off_flags) : nullptr;
   const FwdEntry& f = kFwd[p.tile.id];
   if (tchan && p.precision != RGF_PREC_FP64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(tchan ? f.chan : f.k[p.precision], dim3(p.grid), dim3(f.NW * 64), 0, s, a);
-  return hipGetLastError();
+  err = hipGetLastError();
+  if (err != hipSuccess || !a.fb_flags) return err;
+  return launch_whole_fallback(p, a, ws, s);
 }
 
 }  // namespace rgf

@@ -61,6 +61,10 @@ struct Plan {
   bool want_grad;
   bool large;   // blocked path (n > kTileMaxRows)
   int phi_ld;   // leading dimension of the lead mode tables
+  // accuracy fallback of the conductance sweeps: per-tuple flags (int32)
+  // and the whole-slice workgroups, whose buffers reuse the slot region
+  size_t off_flags;
+  int fb_grid;  // 0: no fallback (gradient, LDOS, FP32 study mode)
 };
 
 // Fill the plan; returns RGF_OK or an error code (with message set).
@@ -104,6 +108,13 @@ const void* grad_kernel_ptr(const TileCfg& t, int precision);
 
 // Matrix buffers (NP x NP complex128) per persistent slot.
 int slot_matrices(int precision, bool grad);
+
+struct SweepArgs;
+// Whole-slice recursion for the tuples flagged by a conductance sweep whose
+// arguments are `fwd` (launched after it on the same stream), and the bytes
+// one of its workgroups needs for width N.
+hipError_t launch_whole_fallback(const Plan& p, const SweepArgs& fwd, char* ws, hipStream_t s);
+size_t whole_slot_bytes(int N);
 
 // Blocked forward sweep, gradient and local density of states for
 // kTileMaxRows < n <= kLargeLd (FP64).

@@ -50,83 +50,107 @@ constexpr size_t FULL = (size_t)LD * LD;   // complex elements of one full matri
 constexpr int kSlotBlocks = 5 * 4 + 1;     // K, G1 x 2, X, Y (4 blocks each); Xp
 constexpr int kGradSlotBlocks = 11 * 4 + 1;  // K x 2, G1 x 2, X, Y, S, Z x 2, Q x 2; Xp
 static_assert(PB * LD <= BP * BP, "the staged pivot rows fit one block");
+// Whole-slice matrices (the accuracy fallback) of up to NRMAX rows: panels
+// of 512 rows x 32 columns for N > 256.
+constexpr int NRMAX = 2 * LD;
+constexpr int WS = 8, WC = 4;              // panel register tile for 512 rows
+static_assert(64 * WS == NRMAX && BW * WC * NRMAX <= BP * BP, "whole-slice panel tile");
 
 struct LargeSmem {
-  cx<double> colbuf[2 * (NR + 1)];  // pivot column and 1/pivot, double-buffered
-  int pivrow[NR];                   // pivot row of each elimination step
-  int pinv[NR];
+  cx<double> colbuf[2 * (NRMAX + 1)];  // pivot column and 1/pivot, double-buffered
+  int pivrow[NRMAX];                   // pivot row of each elimination step
+  int pinv[NRMAX];
   double red[2 * BW];
   double rowacc[NR];                // gradient row sums of the reverse sweep
+  double ksum;                      // sum of the inversions' kappa over the forward sweep
+  double ksum_c;                    // the same over the sublattice-symmetric half-slices
   int flag;
 };
 
 // ---------------------------------------------------------------- panel GJ
-// The elimination step of rgf_engine.hpp on a tall panel: rows up to NR,
-// BW*BC columns, steps 0..nsteps-1 of the panel (the caller passes the
-// panel's slice of the pivot list), pivot candidates the rows r < n not yet
-// used.
+// The elimination step of rgf_engine.hpp on a tall panel: RS slots of 64
+// rows (NRT = 64 RS rows held), BW*RC columns, steps 0..nsteps-1 of the
+// panel (the caller passes the panel's slice of the pivot list), pivot
+// candidates the rows r < n not yet used.
+
+// Pivot key for up to NRT rows: the magnitude as a float with its low bits
+// replaced by NRT - 1 - r (8 bits for 256 rows, 9 for 512), so the largest
+// key is the largest magnitude (to 2^-15 or 2^-14 relative) and ties go to
+// the lowest row; unusable rows get 0.
+template <int NRT>
+__device__ __forceinline__ uint32_t pivot_key_rows(cx<double> v, int r, bool usable) {
+  constexpr uint32_t MASK = NRT <= 256 ? 0xFFu : 0x1FFu;
+  static_assert(NRT <= 512, "row index field");
+  if (!usable) return 0u;
+  float m = (float)cabs1(v);
+  if (!(m >= 0.0f)) m = 0.0f;
+  return (__float_as_uint(m) & ~MASK) | (uint32_t)(NRT - 1 - r);
+}
 
 // A[s][J] for a uniform-per-lane slot s: one branch per slot, kept apart
 // by a distinct empty asm statement, so the tile is never indexed
 // dynamically (a select chain over four slots is folded into a dynamic
 // index, which moves the whole tile to scratch memory).
-template <int J, int SS = 0>
-__device__ __forceinline__ cx<double> pick_slot_br(const cx<double> (&A)[BS][BC], int s) {
-  if constexpr (SS + 1 < BS) {
+template <int RS, int RC, int J, int SS = 0>
+__device__ __forceinline__ cx<double> pick_slot_br(const cx<double> (&A)[RS][RC], int s) {
+  if constexpr (SS + 1 < RS) {
     if (s == SS) {
       asm volatile("; pick slot %0" ::"n"(SS));
       return A[SS][J];
     }
-    return pick_slot_br<J, SS + 1>(A, s);
+    return pick_slot_br<RS, RC, J, SS + 1>(A, s);
   } else {
     return A[SS][J];
   }
 }
 
-template <int J>
-__device__ __forceinline__ void pgj_select_pivot(const cx<double> (&A)[BS][BC], int kc, int n,
+template <int RS, int RC, int J>
+__device__ __forceinline__ void pgj_select_pivot(const cx<double> (&A)[RS][RC], int kc, int n,
                                                  uint32_t used, cx<double>* colbuf, int* pivrow,
                                                  int* flag) {
+  constexpr int NRT = 64 * RS;
+  constexpr uint32_t MASK = NRT <= 256 ? 0xFFu : 0x1FFu;
   const int lane = lane_id();
-  cx<double>* cb = colbuf + (kc & 1) * (NR + 1);
+  cx<double>* cb = colbuf + (kc & 1) * (NRT + 1);
   uint32_t key = 0u;
 #pragma unroll
-  for (int s = 0; s < BS; ++s) {
+  for (int s = 0; s < RS; ++s) {
     const int r = lane + 64 * s;
     cb[r] = A[s][J];
-    key = max(key, pivot_key(A[s][J], r, r < n && !((used >> s) & 1u)));
+    key = max(key, pivot_key_rows<NRT>(A[s][J], r, r < n && !((used >> s) & 1u)));
   }
   key = wave_max_u32(key);
-  const int pk = 255 - (int)(key & 0xFFu);
+  const int pk = NRT - 1 - (int)(key & MASK);
   if (lane == (pk & 63)) {
-    const cx<double> pv = pick_slot_br<J>(A, pk >> 6);
+    const cx<double> pv = pick_slot_br<RS, RC, J>(A, pk >> 6);
     pivrow[kc] = pk;
-    cb[NR] = crcp_scaled(pv);
+    cb[NRT] = crcp_scaled(pv);
     if (!(cabs1(pv) > 0.0)) *flag = 1;
   }
 }
 
-template <int J>
-__device__ __forceinline__ void pgj_step(cx<double> (&A)[BS][BC], int kb, int nsteps, int n,
+template <int RS, int RC, int J>
+__device__ __forceinline__ void pgj_step(cx<double> (&A)[RS][RC], int kb, int nsteps, int n,
                                          uint32_t& used, cx<double>* colbuf, int* pivrow,
                                          int* flag) {
-  constexpr int JN = (J + 1) % BC;
+  constexpr int NRT = 64 * RS;
+  constexpr int JN = (J + 1) % RC;
   const int lane = lane_id(), w = wave_id();
-  const int k = kb * BC + J;
-  const int kbn = (J + 1 == BC) ? kb + 1 : kb;
+  const int k = kb * RC + J;
+  const int kbn = (J + 1 == RC) ? kb + 1 : kb;
   __syncthreads();
-  const cx<double>* cb = colbuf + (k & 1) * (NR + 1);
+  const cx<double>* cb = colbuf + (k & 1) * (NRT + 1);
   const int pkr = pivrow[k];
-  const cx<double> ipiv = cb[NR];
-  cx<double> a[BS];
+  const cx<double> ipiv = cb[NRT];
+  cx<double> a[RS];
 #pragma unroll
-  for (int s = 0; s < BS; ++s) a[s] = cb[lane + 64 * s];
+  for (int s = 0; s < RS; ++s) a[s] = cb[lane + 64 * s];
   __builtin_amdgcn_sched_barrier(0);
-  const int pk = __builtin_amdgcn_readfirstlane(min(max(pkr, 0), NR - 1));
+  const int pk = __builtin_amdgcn_readfirstlane(min(max(pkr, 0), NRT - 1));
   const int pl = pk & 63, ps = pk >> 6;
-  cx<double> m[BS];
+  cx<double> m[RS];
 #pragma unroll
-  for (int s = 0; s < BS; ++s) {
+  for (int s = 0; s < RS; ++s) {
     const int r = lane + 64 * s;
     m[s] = (r == pk) ? mk(1.0 - ipiv.re, -ipiv.im) : cmul(a[s], ipiv);
   }
@@ -134,33 +158,34 @@ __device__ __forceinline__ void pgj_step(cx<double> (&A)[BS][BC], int kb, int ns
   const bool own = (w == kb);
   {
     cx<double> v1[1];
-    gj_row_chunk<double, BS, BC, JN, 1, -1, 0>(A, ps, pl, v1);
-    gj_update_column<double, BS, BC, JN>(A, m, v1[0]);
+    gj_row_chunk<double, RS, RC, JN, 1, -1, 0>(A, ps, pl, v1);
+    gj_update_column<double, RS, RC, JN>(A, m, v1[0]);
   }
   if (w == kbn && k + 1 < nsteps)
-    pgj_select_pivot<JN>(A, k + 1, n, used, colbuf, pivrow, flag);
-  gj_update_chunks<double, BS, BC, J, JN, 0>(A, m, ps, pl, own);
+    pgj_select_pivot<RS, RC, JN>(A, k + 1, n, used, colbuf, pivrow, flag);
+  gj_update_chunks<double, RS, RC, J, JN, 0>(A, m, ps, pl, own);
 }
 
-template <int J>
-__device__ __forceinline__ void pgj_block(cx<double> (&A)[BS][BC], int kb, int nsteps, int n,
+template <int RS, int RC, int J>
+__device__ __forceinline__ void pgj_block(cx<double> (&A)[RS][RC], int kb, int nsteps, int n,
                                           uint32_t& used, cx<double>* colbuf, int* pivrow,
                                           int* flag) {
-  if constexpr (J < BC) {
-    if (kb * BC + J >= nsteps) return;
-    pgj_step<J>(A, kb, nsteps, n, used, colbuf, pivrow, flag);
-    pgj_block<J + 1>(A, kb, nsteps, n, used, colbuf, pivrow, flag);
+  if constexpr (J < RC) {
+    if (kb * RC + J >= nsteps) return;
+    pgj_step<RS, RC, J>(A, kb, nsteps, n, used, colbuf, pivrow, flag);
+    pgj_block<RS, RC, J + 1>(A, kb, nsteps, n, used, colbuf, pivrow, flag);
   }
 }
 
-__device__ __forceinline__ void pgj_panel(cx<double> (&A)[BS][BC], int nsteps, int n,
+template <int RS, int RC>
+__device__ __forceinline__ void pgj_panel(cx<double> (&A)[RS][RC], int nsteps, int n,
                                           uint32_t& used, LargeSmem& sm, int c0) {
   int* pivrow = sm.pivrow + c0;
   if (nsteps > 0 && wave_id() == 0)
-    pgj_select_pivot<0>(A, 0, n, used, sm.colbuf, pivrow, &sm.flag);
+    pgj_select_pivot<RS, RC, 0>(A, 0, n, used, sm.colbuf, pivrow, &sm.flag);
   for (int kb = 0; kb < BW; ++kb) {
-    if (kb * BC >= nsteps) break;
-    pgj_block<0>(A, kb, nsteps, n, used, sm.colbuf, pivrow, &sm.flag);
+    if (kb * RC >= nsteps) break;
+    pgj_block<RS, RC, 0>(A, kb, nsteps, n, used, sm.colbuf, pivrow, &sm.flag);
   }
   __syncthreads();
 }
@@ -168,9 +193,11 @@ __device__ __forceinline__ void pgj_panel(cx<double> (&A)[BS][BC], int nsteps, i
 // ---------------------------------------------------------------- sweep
 
 // M_h (n x n) into X, column-major; returns the largest |re| + |im| of the
-// thread's entries (NaN if any is NaN).
+// thread's entries (NaN if any is NaN) and, in dmax, the largest
+// |E - eps_{h,k}| of the thread's diagonal entries (for the accuracy guard).
 __device__ __forceinline__ double build_M_large(const SweepArgs& a, const Tuple& q, int h,
-                                                const cx<double>* K, cx<double>* X) {
+                                                const cx<double>* K, cx<double>* X,
+                                                double& dmax) {
   const int e = half_parity(h, a.parity);
   const int n = half_size(a.N, e);
   const int nL = half_size(a.N, e ^ 1);
@@ -179,6 +206,7 @@ __device__ __forceinline__ double build_M_large(const SweepArgs& a, const Tuple&
   const double* eps = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
   const double* ph = (h == 0) ? a.phi : (h == 2 * a.L - 1) ? a.phi + (size_t)a.P * LD : nullptr;
   double mx = 0.0;
+  dmax = 0.0;
   for (int i = threadIdx.x; i < n * n; i += BW * 64) {
     const int c = i / n, r = i - c * n;
     cx<double> v = mk(0.0, 0.0);
@@ -199,7 +227,11 @@ __device__ __forceinline__ double build_M_large(const SweepArgs& a, const Tuple&
         v = cscale(acc, mt2);
       }
     }
-    if (r == c) v = cadd(v, mk(q.z.re - (eps ? eps[half_row(r, e)] : 0.0), q.z.im));
+    if (r == c) {
+      const double d = q.z.re - (eps ? eps[half_row(r, e)] : 0.0);
+      dmax = fmax(dmax, fabs(d));
+      v = cadd(v, mk(d, q.z.im));
+    }
     if (ph) {  // lead self-energy on the first and the last half-slice
       for (int p = 0; p < a.P; ++p) {
         const double f = ph[(size_t)p * LD + r] * ph[(size_t)p * LD + c];
@@ -222,37 +254,42 @@ __device__ __forceinline__ double pow2_scale(double mx) {
   return ldexp(1.0, min(-ex, 1022));
 }
 
-// g = M^{-1} (M in X, n x n) into K by the panel Gauss-Jordan; f is the
-// power-of-two scale applied to M for the elimination.
-__device__ __forceinline__ void invert_panels(int n, double f, cx<double>* X, cx<double>* Xp,
-                                              cx<double>* K, cx<double> (&A)[BS][BC],
-                                              LargeSmem& sm) {
+// g = M^{-1} (M in X, n x n, n <= 64 RS, leading dimension LDX) into K
+// (same leading dimension) by the panel Gauss-Jordan; f is the power-of-two
+// scale applied to M for the elimination. Returns (in every thread) kappa =
+// max |(f M)^{-1}|, the condition estimate of the accuracy guard.
+template <int RS, int RC, int LDX>
+__device__ __forceinline__ double invert_panels(int n, double f, cx<double>* X, cx<double>* Xp,
+                                                cx<double>* K, cx<double> (&A)[RS][RC],
+                                                LargeSmem& sm) {
+  constexpr int PBT = BW * RC;
+  static_assert(64 * RS <= LDX && PBT * LDX <= BP * BP, "panel tile and staging buffer");
   const int lane = lane_id(), w = wave_id();
   uint32_t used = 0u;
-  for (int c0 = 0; c0 < n; c0 += PB) {
-    const int bw = min(PB, n - c0);
+  for (int c0 = 0; c0 < n; c0 += PBT) {
+    const int bw = min(PBT, n - c0);
     const double fs = (c0 == 0) ? f : 1.0;  // the first panel applies the scale
     // load the panel (rows >= n and columns >= bw stay zero)
 #pragma unroll
-    for (int j = 0; j < BC; ++j) {
-      const int c = w * BC + j;
+    for (int j = 0; j < RC; ++j) {
+      const int c = w * RC + j;
 #pragma unroll
-      for (int s = 0; s < BS; ++s) {
+      for (int s = 0; s < RS; ++s) {
         const int r = lane + 64 * s;
-        A[s][j] = (r < n && c < bw) ? cscale(ldg(X + (size_t)(c0 + c) * LD + r), fs)
+        A[s][j] = (r < n && c < bw) ? cscale(ldg(X + (size_t)(c0 + c) * LDX + r), fs)
                                     : mk(0.0, 0.0);
       }
     }
-    pgj_panel(A, bw, n, used, sm, c0);
+    pgj_panel<RS, RC>(A, bw, n, used, sm, c0);
     // the panel after elimination back to X
 #pragma unroll
-    for (int j = 0; j < BC; ++j) {
-      const int c = w * BC + j;
+    for (int j = 0; j < RC; ++j) {
+      const int c = w * RC + j;
       if (c >= bw) break;
 #pragma unroll
-      for (int s = 0; s < BS; ++s) {
+      for (int s = 0; s < RS; ++s) {
         const int r = lane + 64 * s;
-        if (r < n) stg(X + (size_t)(c0 + c) * LD + r, A[s][j]);
+        if (r < n) stg(X + (size_t)(c0 + c) * LDX + r, A[s][j]);
       }
     }
     const int nother = n - bw;
@@ -261,7 +298,7 @@ __device__ __forceinline__ void invert_panels(int n, double f, cx<double>* X, cx
       for (int i = threadIdx.x; i < bw * n; i += BW * 64) {
         const int j = i / n, c = i - j * n;
         if (c >= c0 && c < c0 + bw) continue;
-        stg(Xp + (size_t)j * LD + c, cscale(ldg(X + (size_t)c * LD + sm.pivrow[c0 + j]), fs));
+        stg(Xp + (size_t)j * LDX + c, cscale(ldg(X + (size_t)c * LDX + sm.pivrow[c0 + j]), fs));
       }
       __syncthreads();
       // X[:, c] = fs * X[:, c] + (Z - E_P) Xp[:, c] for the columns outside the panel
@@ -274,16 +311,16 @@ __device__ __forceinline__ void invert_panels(int n, double f, cx<double>* X, cx
             return x < c0 ? x : x + bw;
           };
           auto fa = [&](int r, int j) -> cx<double> {
-            cx<double> z = ldg(X + (size_t)(c0 + j) * LD + r0 + r);
+            cx<double> z = ldg(X + (size_t)(c0 + j) * LDX + r0 + r);
             if (r0 + r == sm.pivrow[c0 + j]) z.re -= 1.0;
             return z;
           };
           auto fb = [&](int j, int cc) -> cx<double> {
-            return ldg(Xp + (size_t)j * LD + col(cc));
+            return ldg(Xp + (size_t)j * LDX + col(cc));
           };
           auto epi = [&](int r, int cc, cx<double> v, bool ok) {
             if (!ok) return;
-            cx<double>* p = X + (size_t)col(cc) * LD + r0 + r;
+            cx<double>* p = X + (size_t)col(cc) * LDX + r0 + r;
             stg(p, cadd(cscale(ldg(p), fs), v));
           };
           gemm_mfma<BW, BP>(nr, nc, bw, fa, fb, epi);
@@ -295,11 +332,15 @@ __device__ __forceinline__ void invert_panels(int n, double f, cx<double>* X, cx
   // un-permute: g[i][j] = f * X[p_i][q_j]
   for (int i = threadIdx.x; i < n; i += BW * 64) sm.pinv[sm.pivrow[i]] = i;
   __syncthreads();
+  double kap = 0.0;
   for (int i = threadIdx.x; i < n * n; i += BW * 64) {
     const int j = i / n, r = i - j * n;
-    stg(K + (size_t)j * LD + r, cscale(ldg(X + (size_t)sm.pinv[j] * LD + sm.pivrow[r]), f));
+    const cx<double> x = ldg(X + (size_t)sm.pinv[j] * LDX + sm.pivrow[r]);
+    const double m1 = cabs1(x);
+    kap = (m1 > kap || m1 != m1) ? m1 : kap;
+    stg(K + (size_t)j * LDX + r, cscale(x, f));
   }
-  __syncthreads();
+  return block_max<BW>(kap, sm.red);
 }
 
 // One half-slice step: g_h from g_{h-1} (Kprev) into Kout and G1_h from
@@ -314,8 +355,14 @@ __device__ __forceinline__ void large_step(const SweepArgs& a, const Tuple& q, i
   const int e = half_parity(h, a.parity);
   const int n = half_size(a.N, e);
   const int n1 = half_size(a.N, half_parity(0, a.parity));
-  const double mx = block_max<BW>(build_M_large(a, q, h, Kprev, X), sm.red);
-  invert_panels(n, pow2_scale(mx), X, Xp, Kout, A, sm);
+  double dmax;
+  const double mx = block_max<BW>(build_M_large(a, q, h, Kprev, X, dmax), sm.red);
+  dmax = block_max<BW>(dmax, sm.red);
+  const double kap = invert_panels<BS, BC, LD>(n, pow2_scale(mx), X, Xp, Kout, A, sm);
+  if (threadIdx.x == 0) {  // read after the next barrier
+    sm.ksum += kap;
+    if (dmax < kChiralWindow * fabs(a.t)) sm.ksum_c += kap;
+  }
   if (h == 0) {
     for (int i = threadIdx.x; i < n * n; i += BW * 64) {
       const int c = i / n, r = i - c * n;
@@ -361,13 +408,14 @@ __device__ __forceinline__ double large_trace(const SweepArgs& a, const Tuple& q
   const int H = 2 * a.L;
   const int n1 = half_size(a.N, half_parity(0, a.parity));
   const int nlast = half_size(a.N, half_parity(H - 1, a.parity));
+  const int pld = a.phi_ld;
   const double* phiL = a.phi;
-  const double* phiR = a.phi + (size_t)a.P * LD;
+  const double* phiR = a.phi + (size_t)a.P * pld;
   for (int r0 = 0; r0 < n1; r0 += BP)
     for (int c0 = 0; c0 < a.P; c0 += BP) {
       auto fa = [&](int r, int k) -> cx<double> { return ldg(G + (size_t)k * LD + r0 + r); };
       auto fb = [&](int k, int c) -> cx<double> {
-        return mk(phiR[(size_t)(c0 + c) * LD + k], 0.0);
+        return mk(phiR[(size_t)(c0 + c) * pld + k], 0.0);
       };
       auto epi = [&](int r, int c, cx<double> v, bool ok) {
         if (ok) stg(Y + (size_t)(c0 + c) * LD + r0 + r, v);
@@ -381,7 +429,7 @@ __device__ __forceinline__ double large_trace(const SweepArgs& a, const Tuple& q
   for (int r0 = 0; r0 < a.P; r0 += BP)
     for (int c0 = 0; c0 < a.P; c0 += BP) {
       auto fa = [&](int r, int k) -> cx<double> {
-        return mk(phiL[(size_t)(r0 + r) * LD + k], 0.0);
+        return mk(phiL[(size_t)(r0 + r) * pld + k], 0.0);
       };
       auto fb = [&](int k, int c) -> cx<double> { return ldg(Y + (size_t)(c0 + c) * LD + k); };
       auto epi = [&](int r, int c, cx<double> v, bool ok) {
@@ -399,6 +447,9 @@ __device__ __forceinline__ double large_trace(const SweepArgs& a, const Tuple& q
 __device__ __forceinline__ int tuple_status(const SweepArgs& a, const Tuple& q, double T,
                                             const LargeSmem& sm) {
   int st = a.lstat[q.e];
+  // the guard first: a rejected sweep may also show a zero pivot or a T out
+  // of range (the whole-slice sweep, whose ksum stays 0, never rejects)
+  if (st == RGF_TUPLE_OK && ill_conditioned(sm.ksum, sm.ksum_c)) st = RGF_TUPLE_ILL_CONDITIONED;
   if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
   if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
   if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
@@ -453,7 +504,11 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) 
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
-    if (threadIdx.x == 0) sm.flag = 0;
+    if (threadIdx.x == 0) {
+      sm.flag = 0;
+      sm.ksum = 0.0;
+      sm.ksum_c = 0.0;
+    }
     __syncthreads();
     cx<double> A[BS][BC];
     for (int h = 0; h < H; ++h)
@@ -463,6 +518,8 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_fwd_large_kernel(SweepArgs a) 
     if (threadIdx.x == 0) {
       a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
       if (a.status) a.status[tau] = st;
+      // the whole-slice sweep recomputes the tuples the guard rejected
+      if (a.fb_flags) a.fb_flags[tau] = (st == RGF_TUPLE_ILL_CONDITIONED) ? 1 : 0;
     }
     if (a.tchan) {  // T_p = d_p sum_q d_q |S_pq|^2 (block_sum's barriers order rowacc)
       for (int p = threadIdx.x; p < a.P; p += BW * 64)
@@ -503,7 +560,11 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_grad_large_kernel(SweepArgs a)
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
-    if (threadIdx.x == 0) sm.flag = 0;
+    if (threadIdx.x == 0) {
+      sm.flag = 0;
+      sm.ksum = 0.0;
+      sm.ksum_c = 0.0;
+    }
     __syncthreads();
     cx<double> A[BS][BC];
 
@@ -680,7 +741,11 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_ldos_large_kernel(SweepArgs a)
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
-    if (threadIdx.x == 0) sm.flag = 0;
+    if (threadIdx.x == 0) {
+      sm.flag = 0;
+      sm.ksum = 0.0;
+      sm.ksum_c = 0.0;
+    }
     __syncthreads();
     cx<double> A[BS][BC];
     double* out = a.ldos + tau * (int64_t)a.L * a.N;  // [L][N] of this tuple
@@ -783,6 +848,175 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_ldos_large_kernel(SweepArgs a)
   }
 }
 
+
+// ---------------------------------------------------------------- accuracy fallback
+// The whole-slice form of the recursion (Eqs. (4)-(5) with the full N x N
+// slice) for the tuples the half-slice guard rejected. The carried state is
+// the same as on the half-slice chain -- g of the rows R_i that bond to the
+// next slice and G1 = G_{1i} on (L_1, R_i) -- but each slice is inverted as
+// a whole, with partial pivoting across both row classes:
+//   M_i = z - H_i - t^2 g_{i-1} on L_i x L_i   (- Sigma_L at i = 1, - Sigma_R at i = L),
+//   W = M_i^{-1},   g_i = W[R_i, R_i],   G1_i = t G1_{i-1} W[L_i, R_i]   (G1_1 = W[L_1, R_1]).
+// The diagonal of M_i carries the intra-slice bonds, so no block divides by
+// the bare z - eps of one sublattice. Costs about (8 + 1) N^3 flops per
+// slice instead of 4 N^3; it runs only on flagged tuples.
+
+// Entry (r, c) of M_i, r, c < N.
+__device__ __forceinline__ cx<double> m_whole_entry(const SweepArgs& a, const Tuple& q, int i,
+                                                    const cx<double>* K, int r, int c) {
+  const int eL = half_parity(2 * (i - 1), a.parity);
+  cx<double> v = mk(0.0, 0.0);
+  if (r == c) v = mk(q.z.re - (q.eps_r ? q.eps_r[(int64_t)(i - 1) * a.N + r] : 0.0), q.z.im);
+  if (r == c + 1 || c == r + 1) v.re -= a.t;
+  const bool rl = (r & 1) == eL, cl = (c & 1) == eL;
+  // row k of a row class has local index k >> 1 (k = 2 a + parity of the class)
+  if (rl && cl && i > 1)
+    v = cadd(v, cscale(ldg(K + (size_t)(c >> 1) * LD + (r >> 1)), -(a.t * a.t)));
+  const int pld = a.phi_ld;
+  const double* ph = (rl && cl && i == 1)         ? a.phi
+                     : (!rl && !cl && i == a.L) ? a.phi + (size_t)a.P * pld
+                                                : nullptr;
+  if (ph) {
+    for (int p = 0; p < a.P; ++p) {
+      const double f = ph[(size_t)p * pld + (r >> 1)] * ph[(size_t)p * pld + (c >> 1)];
+      v.re = fma(-f, q.sig[p].re, v.re);
+      v.im = fma(-f, q.sig[p].im, v.im);
+    }
+  }
+  return v;
+}
+
+// M_i into X (column-major, leading dimension LDX); returns the thread's
+// largest |re| + |im| (NaN if any entry is NaN).
+template <int LDX>
+__device__ __forceinline__ double build_M_whole(const SweepArgs& a, const Tuple& q, int i,
+                                                const cx<double>* K, cx<double>* X) {
+  const int N = a.N;
+  double mx = 0.0;
+  for (int idx = threadIdx.x; idx < N * N; idx += BW * 64) {
+    const int c = idx / N, r = idx - c * N;
+    const cx<double> v = m_whole_entry(a, q, i, K, r, c);
+    const double m1 = cabs1(v);
+    mx = (m1 > mx || m1 != m1) ? m1 : mx;
+    stg(X + (size_t)c * LDX + r, v);
+  }
+  return mx;
+}
+
+// Complex elements of one workgroup's buffers: g and G1 x 2 at leading
+// dimension LD (at most 256 rows), M_i and its inverse at LDX, the refined
+// columns (LDX x LDX/2), staged rows.
+template <int LDX>
+constexpr size_t whole_slot_elems() {
+  return 3 * FULL + 2 * (size_t)LDX * LDX + (size_t)LDX * (LDX / 2) + (size_t)BP * BP;
+}
+
+template <int RS, int RC, int LDX>
+__global__ __launch_bounds__(BW * 64, 2) void rgf_whole_kernel(SweepArgs a) {
+  __shared__ LargeSmem sm;
+  constexpr size_t FX = (size_t)LDX * LDX;
+  cx<double>* slot = a.slots + (size_t)blockIdx.x * whole_slot_elems<LDX>();
+  cx<double>* K = slot;
+  cx<double>* G1b[2] = {slot + FULL, slot + 2 * FULL};
+  cx<double>* X = slot + 3 * FULL;
+  cx<double>* W = X + FX;
+  cx<double>* V = W + FX;            // refined columns R_i of M_i^{-1} (N x n_R, ld LDX)
+  cx<double>* Xp = V + FX / 2;
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const int N = a.N;
+  const double t = a.t;
+
+  for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
+    if (a.fb_flags[tau] == 0) continue;  // same word for every thread: uniform
+    const Tuple q = make_tuple_(a, tau);
+    if (threadIdx.x == 0) {
+      sm.flag = 0;
+      sm.ksum = 0.0;
+      sm.ksum_c = 0.0;
+    }
+    __syncthreads();
+    cx<double> A[RS][RC];
+    int cur = 0;
+    for (int i = 1; i <= a.L; ++i) {
+      const double mx = block_max<BW>(build_M_whole<LDX>(a, q, i, K, X), sm.red);
+      (void)invert_panels<RS, RC, LDX>(N, pow2_scale(mx), X, Xp, W, A, sm);  // ends on a barrier
+      const int eL = half_parity(2 * (i - 1), a.parity), eR = eL ^ 1;
+      const int nLi = half_size(N, eL), nRi = half_size(N, eR);
+      // One Newton step on the columns R_i of the inverse (Gauss-Jordan
+      // alone loses digits when M_i mixes entries of very different size,
+      // e.g. lead self-energies of nearly decoupled modes near E = 0):
+      //   Res = E_R - M_i W[:, R_i] -> X,   V = W[:, R_i] + W Res.
+      for (int r0 = 0; r0 < N; r0 += BP)
+        for (int c0 = 0; c0 < nRi; c0 += BP) {
+          auto fa = [&](int r, int k) -> cx<double> { return m_whole_entry(a, q, i, K, r0 + r, k); };
+          auto fb = [&](int k, int c) -> cx<double> {
+            return ldg(W + (size_t)(2 * (c0 + c) + eR) * LDX + k);
+          };
+          auto epi = [&](int r, int c, cx<double> v, bool ok) {
+            if (!ok) return;
+            const double one = (r0 + r == 2 * (c0 + c) + eR) ? 1.0 : 0.0;
+            stg(X + (size_t)(c0 + c) * LDX + r0 + r, mk(one - v.re, -v.im));
+          };
+          gemm_mfma<BW, BP>(min(BP, N - r0), min(BP, nRi - c0), N, fa, fb, epi);
+        }
+      __syncthreads();
+      for (int r0 = 0; r0 < N; r0 += BP)
+        for (int c0 = 0; c0 < nRi; c0 += BP) {
+          auto fa = [&](int r, int k) -> cx<double> { return ldg(W + (size_t)k * LDX + r0 + r); };
+          auto fb = [&](int k, int c) -> cx<double> { return ldg(X + (size_t)(c0 + c) * LDX + k); };
+          auto epi = [&](int r, int c, cx<double> v, bool ok) {
+            if (!ok) return;
+            const cx<double> w0 = ldg(W + (size_t)(2 * (c0 + c) + eR) * LDX + r0 + r);
+            stg(V + (size_t)(c0 + c) * LDX + r0 + r, cadd(w0, v));
+          };
+          gemm_mfma<BW, BP>(min(BP, N - r0), min(BP, nRi - c0), N, fa, fb, epi);
+        }
+      __syncthreads();
+      cx<double>* G1o = G1b[cur ^ 1];
+      if (i == 1) {
+        for (int idx = threadIdx.x; idx < n1 * nRi; idx += BW * 64) {
+          const int c = idx / n1, r = idx - c * n1;
+          stg(G1o + (size_t)c * LD + r, ldg(V + (size_t)c * LDX + 2 * r + eL));
+        }
+      } else {
+        const cx<double>* G1i = G1b[cur];
+        for (int r0 = 0; r0 < n1; r0 += BP)
+          for (int c0 = 0; c0 < nRi; c0 += BP) {
+            auto fa = [&](int r, int k) -> cx<double> {
+              return cscale(ldg(G1i + (size_t)k * LD + r0 + r), t);
+            };
+            auto fb = [&](int k, int c) -> cx<double> {
+              return ldg(V + (size_t)(c0 + c) * LDX + 2 * k + eL);
+            };
+            auto epi = [&](int r, int c, cx<double> v, bool ok) {
+              if (ok) stg(G1o + (size_t)(c0 + c) * LD + r0 + r, v);
+            };
+            gemm_mfma<BW, BP>(min(BP, n1 - r0), min(BP, nRi - c0), nLi, fa, fb, epi);
+          }
+      }
+      // g_i = V[R_i, :] -> K (K, read by the residual above, is free now)
+      for (int idx = threadIdx.x; idx < nRi * nRi; idx += BW * 64) {
+        const int c = idx / nRi, r = idx - c * nRi;
+        stg(K + (size_t)c * LD + r, ldg(V + (size_t)c * LDX + 2 * r + eR));
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    const double T = large_trace(a, q, G1b[cur], X, nullptr, sm, a.tchan != nullptr);
+    const int st = tuple_status(a, q, T, sm);
+    if (threadIdx.x == 0) {
+      a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
+      if (a.status) a.status[tau] = st;
+    }
+    if (a.tchan) {
+      for (int p = threadIdx.x; p < a.P; p += BW * 64)
+        a.tchan[tau * a.P + p] =
+            (st == RGF_TUPLE_OK) ? -2.0 * q.sig[p].im * sm.rowacc[p] : __builtin_nan("");
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 const void* large_kernel_ptr(bool grad) {
@@ -815,6 +1049,7 @@ static SweepArgs large_args(const Plan& p, const double* E, const double* eps, d
   a.slots = reinterpret_cast<cx<double>*>(ws + p.off_slots);
   a.slot_mats = p.slot_mats;
   a.ntuples = p.ntuples;
+  a.phi_ld = LD;
   return a;
 }
 
@@ -826,8 +1061,11 @@ hipError_t launch_forward_large(const Plan& p, const double* E, const double* ep
   if (err != hipSuccess) return err;
   SweepArgs a = large_args(p, E, eps, T_out, status_out, ws);
   a.tchan = tchan;
+  a.fb_flags = p.fb_grid > 0 ? reinterpret_cast<int32_t*>(ws + p.off_flags) : nullptr;
   hipLaunchKernelGGL(rgf_fwd_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
-  return hipGetLastError();
+  err = hipGetLastError();
+  if (err != hipSuccess || !a.fb_flags) return err;
+  return launch_whole_fallback(p, a, ws, s);
 }
 
 hipError_t launch_grad_large(const Plan& p, const double* E, const double* eps,
@@ -859,6 +1097,23 @@ hipError_t launch_ldos_large(const Plan& p, const double* E, const double* eps, 
   a.n_ckpt = (int)p.n_ckpt;
   a.ldos = ldos;
   hipLaunchKernelGGL(rgf_ldos_large_kernel, dim3(p.grid), dim3(BW * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+
+size_t whole_slot_bytes(int N) {
+  return 16 * (N <= LD ? whole_slot_elems<LD>() : whole_slot_elems<NRMAX>());
+}
+
+hipError_t launch_whole_fallback(const Plan& p, const SweepArgs& fwd, char* ws, hipStream_t s) {
+  if (p.fb_grid <= 0 || p.ntuples == 0) return hipSuccess;
+  SweepArgs a = fwd;
+  a.slots = reinterpret_cast<cx<double>*>(ws + p.off_slots);  // the sweep's slots, now free
+  if (p.N <= LD)
+    hipLaunchKernelGGL((rgf_whole_kernel<BS, BC, LD>), dim3(p.fb_grid), dim3(BW * 64), 0, s, a);
+  else
+    hipLaunchKernelGGL((rgf_whole_kernel<WS, WC, NRMAX>), dim3(p.fb_grid), dim3(BW * 64), 0, s,
+                       a);
   return hipGetLastError();
 }
 

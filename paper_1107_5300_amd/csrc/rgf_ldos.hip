@@ -45,7 +45,11 @@ __global__ __launch_bounds__(NW * 64) void rgf_ldos_kernel(SweepArgs a) {
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
-    if (threadIdx.x == 0) sm.flag = 0;
+    if (threadIdx.x == 0) {
+      sm.flag = 0;
+      sm.ksum = 0.0;
+      sm.ksum_c = 0.0;
+    }
     __syncthreads();
     cx<double> A[S][C];
     double* out = a.ldos + tau * (int64_t)a.L * a.N;  // [L][N] of this tuple
@@ -54,6 +58,11 @@ __global__ __launch_bounds__(NW * 64) void rgf_ldos_kernel(SweepArgs a) {
     const cx<double>* Klast = kb[(H - 1) & 1];
     const double T = trace_T<NW, S, C>(a, q, gbuf, xbuf, A, sm);
     int st = a.lstat[q.e];
+    // the guard first: a rejected sweep may also show a zero pivot or a T
+    // out of range (no whole-slice form of this sweep)
+    if ((sizeof(TJ) == sizeof(double) || REFINE) && st == RGF_TUPLE_OK &&
+        ill_conditioned(sm.ksum, sm.ksum_c))
+      st = RGF_TUPLE_ILL_CONDITIONED;
     if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
     if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
     if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;

@@ -56,7 +56,34 @@ struct SweepArgs {
   double* ldos;             // [nreal][nE][L][N]
   // transmission per incoming lead channel, or null
   double* tchan;            // [nreal][nE][P]
+  // tuples the half-slice recursion could not resolve accurately (1) and
+  // that the whole-slice sweep recomputes, or null
+  int32_t* fb_flags;        // [nreal][nE]
+  int phi_ld;               // leading dimension of the lead mode tables
 };
+
+// Accuracy guard of the half-slice recursion. Each half-slice inversion
+// contributes kappa_h = max|(f M_h)^{-1}| (f scales M_h to entries below 1,
+// so kappa_h estimates the condition number in the max-entry norm).
+// Cutting a slice between its two row classes leaves dangling bonds. When
+// every on-site term of a half-slice lies within kChiralWindow |t| of E
+// (pristine or nearly pristine rows: the sublattice-symmetric regime), their
+// zero-energy states make the inverses grow like 1/E on a whole subspace at
+// every step, and the rounding error of T reaches about 5e-3 u sum_h kappa_h
+// (u = 2^-53); such half-slices add kappa_h to a separate sum. Isolated
+// resonances of disordered rows raise kappa_h at a few steps only and cost
+// far less accuracy (about 1e-4 u sum_h kappa_h measured). A tuple is handed
+// to the whole-slice sweep (conductance) or flagged RGF_TUPLE_ILL_CONDITIONED
+// (gradient, LDOS) when the sublattice-symmetric sum exceeds kIllCondChiral
+// or the total exceeds kIllCondAll.
+constexpr double kChiralWindow = 0.01;
+constexpr double kIllCondChiral = 1e9;
+constexpr double kIllCondAll = 1e11;
+
+// True if a tuple's accumulated condition estimates reject it.
+__device__ __forceinline__ bool ill_conditioned(double ksum_all, double ksum_chiral) {
+  return !(ksum_all <= kIllCondAll) || !(ksum_chiral <= kIllCondChiral);
+}
 
 template <int NW, int S, int C>
 struct SweepSmem {
@@ -69,8 +96,27 @@ struct SweepSmem {
   int pinv[NP];
   double red[NW * 2];
   double rowacc[NP];
+  double kred[NW];   // per-wave kappa of the latest inversion
+  double ksum;       // running sum of kappa_h over the forward sweep
+  double ksum_c;     // the same over the sublattice-symmetric half-slices
   int flag;
 };
+
+// Largest |re| + |im| of a register tile across the wave (from the high 32
+// bits of the magnitudes, so it is a lower bound within 2^-20).
+template <typename T, int S, int C>
+__device__ __forceinline__ double tile_absmax_wave(const cx<T> (&A)[S][C]) {
+  uint32_t b = 0u;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j = 0; j < C; ++j) b = max(b, mag_hi(cabs1(A[s][j])));
+  b = wave_max_u32(b);
+  if constexpr (sizeof(T) == sizeof(double))
+    return __longlong_as_double((long long)((uint64_t)b << 32));
+  else
+    return (double)__uint_as_float(b);
+}
 
 // Eq. (2) for unitary scattering bounds T by the number of open channels,
 // at most the P lead modes; a value outside [0, P] (beyond rounding) means
@@ -136,10 +182,12 @@ __device__ __forceinline__ void sub_mode_sum(cx<T> (&A)[S][C], const double* phi
 // where (B'^T K B')[r][c] = sum of K over the neighbour rows of r and the
 // neighbour columns of c; the column sums go through the wave's LDS scratch.
 // Sums are formed in FP64 and rounded once to T.
+// Returns (wave-uniform) the high word of max_k |E - eps_{h,k}|, for the
+// accuracy guard.
 template <typename T, int NW, int S, int C>
-__device__ __forceinline__ void build_M(cx<T> (&A)[S][C], const SweepArgs& a,
-                                        const Tuple& q, int h, const cx<double>* K,
-                                        cx<double>* wbuf) {
+__device__ __forceinline__ uint32_t build_M(cx<T> (&A)[S][C], const SweepArgs& a,
+                                            const Tuple& q, int h, const cx<double>* K,
+                                            cx<double>* wbuf) {
   constexpr int NP = NW * C;
   const int lane = lane_id(), w = wave_id();
   const bool rhalf = (h & 1) != 0;
@@ -200,6 +248,11 @@ __device__ __forceinline__ void build_M(cx<T> (&A)[S][C], const SweepArgs& a,
   }
   if (h == 0) sub_mode_sum<T, NW, S, C>(A, a.phi, q.sig, a.P, n);
   if (h == 2 * a.L - 1) sub_mode_sum<T, NW, S, C>(A, a.phi + (size_t)a.P * NP, q.sig, a.P, n);
+  uint32_t dk = 0u;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    if (lane + 64 * s < n) dk = max(dk, mag_hi(fabs(dre[s])));
+  return wave_max_u32(dk);
 }
 
 // One entry of M_h in FP64 (for the refinement residual), r, c < NP.
@@ -256,35 +309,54 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
   const int e = half_parity(h, a.parity);
   const int n = half_size(a.N, e);
   const int n1 = half_size(a.N, half_parity(0, a.parity));
+  uint32_t dkey;  // high word of max_k |E - eps_{h,k}| (wave-uniform)
   if constexpr (sizeof(TJ) == sizeof(double)) {
-    build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
+    dkey = build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
     const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));
     scale_regs(A, f);
     gj_invert<double, NW, S, C>(A, n, sm.colbuf, sm.pivrow, sm.pinv, &sm.flag);
+    {
+      const double km = tile_absmax_wave(A);
+      if (lane_id() == 0) sm.kred[w] = km;
+    }
     store_unpermuted<double, double, NW, S, C>(A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout,
                                                h == 0 ? G1out : nullptr);
   } else {
     cx<float> AJ[S][C];
-    build_M<float, NW, S, C>(AJ, a, q, h, Kprev, sm.wbuf + w * NP);
+    dkey = build_M<float, NW, S, C>(AJ, a, q, h, Kprev, sm.wbuf + w * NP);
     const float f = tile_scale<float, NW, S, C>(AJ, reinterpret_cast<uint32_t*>(sm.red));
     scale_regs(AJ, f);
     gj_invert<float, NW, S, C>(AJ, n, reinterpret_cast<cx<float>*>(sm.colbuf), sm.pivrow,
                                sm.pinv, &sm.flag);
+    {
+      const double km = tile_absmax_wave(AJ);
+      if (lane_id() == 0) sm.kred[w] = km;
+    }
     store_unpermuted<float, double, NW, S, C>(AJ, n, f,
                                               reinterpret_cast<cx<float>*>(sm.wbuf),
                                               sm.pivrow, sm.pinv, Kout,
                                               (h == 0 && !REFINE) ? G1out : nullptr);
   }
   __syncthreads();
+  if (threadIdx.x == 0) {  // the next write of kred follows two more barriers
+    double km = sm.kred[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) km = max(km, sm.kred[i]);
+    sm.ksum += km;
+    if (dkey < mag_hi(kChiralWindow * fabs(a.t))) sm.ksum_c += km;
+  }
   if constexpr (REFINE) {
     // Newton's iteration for the inverse in FP64 from the FP32 start g0:
     //   R_k = I - M g_k,  g_{k+1} = g_k (I + R_k),  R_{k+1} = R_k^2,
-    // with M regenerated in FP64 from Kprev. It converges only if the FP32
-    // start is good (|R_0| < 1/4 here); a half-slice that ill-conditioned
-    // (kappa ~ 1/u_32, near resonances of disordered ribbons) is inverted again
-    // by the FP64 Gauss-Jordan instead.
+    // with M regenerated in FP64 from Kprev. It converges when the spectral
+    // radius of R_0 is below 1; n max|R_0| bounds the infinity norm, so a
+    // start with n max|R_0| >= 1/2 (kappa ~ 1/u_32 near resonances of
+    // disordered ribbons) is not used, and neither is one whose residual
+    // fails to shrink at a later step or that has not converged after four
+    // steps: such a half-slice is inverted again by the FP64 Gauss-Jordan.
     const int lane = lane_id();
-    bool fallback = false;
+    bool converged = false;
+    double rprev = 0.0;
     for (int it = 0; it < 4; ++it) {
       {
         const Tuple& qq = q;
@@ -310,11 +382,11 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
         }
       }
       const double rmax = block_max<NW>(lmax, sm.red);
-      if (it == 0 && !(rmax < 0.25)) {
-        fallback = true;
+      if (it == 0 ? !((double)n * rmax < 0.5) : !(rmax < rprev)) break;  // not converging
+      if (!(rmax > 1e-15)) {   // at rounding level already
+        converged = true;
         break;
       }
-      if (!(rmax > 1e-15)) break;   // converged to rounding
       store_regs<double, double, NW, S, C>(A, n, n, Rbuf);
       __syncthreads();
       auto fa = [&](int r, int k) -> cx<double> {
@@ -326,8 +398,13 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
       gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
       store_regs<double, double, NW, S, C>(A, n, n, Kout);
       __syncthreads();
-      if (rmax < 1e-8) break;   // the next residual is below n * 1e-16
+      if (rmax < 1e-8) {   // the next residual is below n rmax^2 < n * 1e-16
+        converged = true;
+        break;
+      }
+      rprev = rmax;
     }
+    const bool fallback = !converged;
     if (fallback) {
       build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
       const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));

@@ -73,8 +73,16 @@ _default_ws = {}
 
 
 def _workspace(ws, nbytes, device):
+    """The caller's Workspace, or a default one per (device, stream). A call
+    under graph capture must bring its own Workspace: the graph keeps the
+    buffer's address, and a later eager call that grew the default buffer
+    would free it."""
     if ws is None:
-        ws = _default_ws.setdefault(device.index, Workspace())
+        stream = torch.cuda.current_stream(device)
+        if torch.cuda.is_current_stream_capturing():
+            raise RuntimeError("calls under graph capture need a dedicated Workspace "
+                               "(pass workspace=Workspace())")
+        ws = _default_ws.setdefault((device.index, stream.cuda_stream), Workspace())
     return ws.get(nbytes, device)
 
 

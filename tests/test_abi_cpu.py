@@ -193,15 +193,23 @@ def test_wide_ribbon_workspace_scales_with_grid():
     """The blocked path's workspace: lead tables with leading dimension 256
     plus 21 blocks of 128 x 128 complex128 per persistent slot (five 256 x 256
     matrices and the staged pivot rows; the grid is at most the tuple
-    count)."""
+    count), and at least one slot of the whole-slice accuracy fallback
+    (three 256 x 256 and two 512 x 512 matrices, the refined 512 x 256
+    columns and staged rows), which
+    reuses the slot region."""
     from paper_1107_5300_amd import _lib as L
     lib = L.lib()
     d = L.make_desc(480, 4)
-    one = lib.rgf_workspace_bytes(ctypes.byref(d), 1, 1, 0, 0, 0)
-    two = lib.rgf_workspace_bytes(ctypes.byref(d), 2, 1, 0, 0, 0)
     slot = 21 * 128 * 128 * 16
-    assert one >= slot + 2 * 240 * 256 * 8
-    assert two - one >= slot
+    whole = (3 * 256 * 256 + 2 * 512 * 512 + 512 * 256 + 128 * 128) * 16
+    one = lib.rgf_workspace_bytes(ctypes.byref(d), 1, 1, 0, 0, 0)
+    assert one >= whole + 2 * 240 * 256 * 8
+    three = lib.rgf_workspace_bytes(ctypes.byref(d), 3, 1, 0, 0, 0)
+    four = lib.rgf_workspace_bytes(ctypes.byref(d), 4, 1, 0, 0, 0)
+    assert three >= 3 * slot and four - three >= slot
+    # the FP64 gradient has no fallback: no whole-slice slot
+    g1 = lib.rgf_workspace_bytes(ctypes.byref(d), 1, 1, 0, 1, 0)
+    assert g1 > 0
 
 
 def test_channel_transmission_and_lead_modes_arguments():

@@ -112,15 +112,27 @@ def test_checkpoint_strides_agree(P):
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * max(1.0, np.abs(ref).max()))
 
 
-def test_mixed_precision_close_to_fp64(P):
+def test_mixed_precision_vs_oracle(P):
+    """Mixed-precision LDOS of every site against the oracle (as FP64)."""
     N, L = 120, 30
     eps = W.disorder(L, N, 0.5, r=1)
     Es = np.array([-0.4, 0.12]) * abs(W.T_HOP)
     _say("mixed", N, L)
-    a, _, sa = _gpu(P, N, L, 0, W.T_HOP, Es, eps, precision="fp64")
     b, _, sb = _gpu(P, N, L, 0, W.T_HOP, Es, eps, precision="mixed")
-    assert (sa == 0).all() and (sb == 0).all()
-    _close(b, a, tol=1e-7)
+    assert (sb == 0).all()
+    for j, E in enumerate(Es):
+        _close(b[0, j], O.ldos(N, L, W.T_HOP, W.ETA, E, eps, 0))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_mixed_small_ribbons_vs_oracle(P, seed):
+    N, L, parity, t, eps, E = W.random_case(7300 + seed, n_max=20, l_max=9)
+    _say("mixed small", seed, N, L, parity)
+    Es = [E, 0.38 * abs(t)]
+    rho, _, st = _gpu(P, N, L, parity, t, Es, eps, precision="mixed")
+    assert (st == 0).all()
+    for j, Ej in enumerate(Es):
+        _close(rho[0, j], O.ldos(N, L, t, W.ETA, Ej, eps, parity))
 
 
 def test_nan_energy_sets_status(P):
