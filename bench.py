@@ -775,9 +775,13 @@ def main():
     ev_mean_s = float(np.mean(r["ev_ms"])) / 1e3
     flops_call = flops_per_slice_step(N) * steps_per_call
     achieved = flops_call / ev_mean_s / 1e12
-    kname = "rgf_fwd_kernel<%s, %s, %d, %d, %d, false>" % (
-        "double" if prec == "fp64" else "float", "true" if prec == "mixed" else "false",
-        *(r["tile"][:3] if r["tile"] else (0, 0, 0)))
+    if r["tile"] is not None and getattr(r["tile"], "mgj", False):
+        kname = "rgf_fwd_mgj_kernel<%s, %s>" % (
+            "double" if prec == "fp64" else "float", "true" if prec == "mixed" else "false")
+    else:
+        kname = "rgf_fwd_kernel<%s, %s, %d, %d, %d, false>" % (
+            "double" if prec == "fp64" else "float", "true" if prec == "mixed" else "false",
+            *(r["tile"][:3] if r["tile"] else (0, 0, 0)))
     traffic = measured_traffic(kname)
     issued = measured_issued(kname)
     line = {
@@ -809,6 +813,7 @@ def main():
             "traffic_unit": "bytes per launch (HBM side, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": kname,
             "tile": r["tile"],
+            "matrix_core_inversion": bool(getattr(r["tile"], "mgj", False)),
             "flops_per_slice_step": flops_per_slice_step(N),
             "dense_equiv_tflops": dense_equiv_flops(N) * steps_per_call / ev_mean_s / 1e12,
             "issued_frac": None if issued is None else
@@ -841,7 +846,9 @@ def main():
                       "max_abs_dT_vs_oracle": (None if results[p]["dT"] is None
                                                else float(results[p]["dT"])),
                       "max_abs_dT_vs_fp64_all_energies": results[p].get("dT_vs_fp64_all"),
-                      "tile": results[p]["tile"]} for p in results},
+                      "tile": results[p]["tile"],
+                      "matrix_core_inversion": bool(getattr(results[p]["tile"], "mgj", False))}
+                for p in results},
     }
     print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)), flush=True)
 

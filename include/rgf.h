@@ -262,8 +262,12 @@ int rgf_lead_modes(const rgf_ribbon_desc* desc, const double* energies_ev,
  * rgf_workspace_bytes, so tune before sizing workspaces. Thread-safe. Not
  * for use inside stream capture. The workspace must hold
  * rgf_autotune_workspace_bytes(desc, precision) bytes.
- * chosen_out (may be NULL) receives NW * 10000 + S * 1000 + C * 10 + slots
- * per compute unit of the chosen configuration. */
+ * chosen_out (may be NULL) receives 100000 * mgj + NW * 10000 + S * 1000 +
+ * C * 10 + slots per compute unit of the chosen configuration, mgj = 1 for
+ * the forward sweep whose half-slice inversions run as a blocked
+ * Gauss-Jordan on the matrix cores (8 waves, half-slices of up to 128
+ * rows; the default of RGF_PREC_MIXED for 97..128 rows), 0 for the
+ * register tilings. */
 size_t rgf_autotune_workspace_bytes(const rgf_ribbon_desc* desc, int precision);
 int rgf_autotune(const rgf_ribbon_desc* desc, int precision, void* workspace,
                  size_t workspace_bytes, void* hip_stream, int32_t* chosen_out);

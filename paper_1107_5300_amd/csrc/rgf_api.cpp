@@ -101,6 +101,17 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
   } else if (!pick_tile(q.nmax, precision, &q.tile)) {
     return fail(RGF_ERR_UNSUPPORTED, "width_n = %d exceeds the register tiling", q.N);
   }
+  if (!q.large && q.want_grad && q.tile.mgj) {
+    // the gradient and LDOS sweeps keep the register tiling: the smallest
+    // one that holds n
+    for (int i = 0; i < tile_count(); ++i) {
+      const TileCfg c = tile_at(i);
+      if (!c.mgj && c.NP() >= q.nmax && 64 * c.S >= c.NP()) {
+        q.tile = c;
+        break;
+      }
+    }
+  }
   if (!q.large && q.want_grad && q.ntuples <= device_cu_count()) {
     // Fewer tuples than compute units: each workgroup runs one tuple at a
     // time and the sweep is latency-bound, so prefer the tiling with the
@@ -109,7 +120,7 @@ int make_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int precision
     for (int i = 0; i < tile_count(); ++i) {
       const TileCfg c = tile_at(i);
       const int np = c.NP();
-      if (np < q.nmax || 64 * c.S < np || 4 * np > 5 * q.nmax + 32) continue;
+      if (c.mgj || np < q.nmax || 64 * c.S < np || 4 * np > 5 * q.nmax + 32) continue;
       if (c.NW > best.NW || (c.NW == best.NW && np < best.NP())) best = c;
     }
     q.tile = best;
@@ -604,7 +615,7 @@ int rgf_autotune(const rgf_ribbon_desc* desc, int precision, void* workspace,
   set_tuned_choice(n, precision, best_tile, best_pc);
   if (chosen_out) {
     TileCfg t = tile_at(best_tile);
-    *chosen_out = t.NW * 10000 + t.S * 1000 + t.C * 10 + best_pc;
+    *chosen_out = (t.mgj ? 100000 : 0) + t.NW * 10000 + t.S * 1000 + t.C * 10 + best_pc;
   }
   return RGF_OK;
 }

@@ -73,12 +73,55 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_f
   }
 }
 
+// The sweep with the matrix-core Gauss-Jordan (rgf_mgj.hpp) for half-slices
+// of up to 128 rows: one 8-wave workgroup per compute unit, the (8, 2, 16)
+// tiling for the trace.
+template <typename TJ, bool REFINE>
+__global__ __launch_bounds__(512, 1) void rgf_fwd_mgj_kernel(SweepArgs a) {
+  constexpr int NW = 8, S = 2, C = 16, NP = NW * C;
+  __shared__ SweepSmem<NW, S, C> sm;
+  __shared__ MgjSmem<double> ms;  // the FP32 inversion uses it as MgjSmem<float>
+  cx<double>* slot = a.slots + (size_t)blockIdx.x * a.slot_mats * NP * NP;
+  cx<double>* kb[2] = {slot, REFINE ? slot + (size_t)3 * NP * NP : slot};
+  cx<double>* gbuf = slot + (size_t)NP * NP;
+  cx<double>* rbuf = slot + (size_t)2 * NP * NP;
+  cx<double>* mbuf = REFINE ? slot + (size_t)4 * NP * NP : nullptr;  // M_h in FP64
+
+  for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
+    const Tuple q = make_tuple_(a, tau);
+    if (threadIdx.x == 0) {
+      sm.flag = 0;
+      sm.ksum = 0.0;
+      sm.ksum_c = 0.0;
+    }
+    __syncthreads();
+    for (int h = 0; h < 2 * a.L; ++h)
+      half_step_mgj<TJ, REFINE>(a, q, h, kb[(h + 1) & 1], kb[h & 1], gbuf, gbuf, rbuf, mbuf, sm,
+                                ms);
+    cx<double> A[S][C];
+    const double T = trace_T<NW, S, C>(a, q, gbuf, rbuf, A, sm);
+    if (threadIdx.x == 0) {
+      int st = a.lstat[q.e];
+      if (st == RGF_TUPLE_OK && ill_conditioned(sm.ksum, sm.ksum_c))
+        st = RGF_TUPLE_ILL_CONDITIONED;
+      if (st == RGF_TUPLE_OK && sm.flag) st = RGF_TUPLE_SINGULAR;
+      if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
+      if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
+      a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
+      if (a.status) a.status[tau] = st;
+      if (a.fb_flags) a.fb_flags[tau] = (st == RGF_TUPLE_ILL_CONDITIONED) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+}
+
 using FwdKernel = void (*)(SweepArgs);
 
 struct FwdEntry {
   int NW, S, C;
   FwdKernel k[3];  // by precision: FP64, MIXED, FP32
   FwdKernel chan;  // FP64 with the per-channel transmission
+  bool mgj;        // matrix-core Gauss-Jordan (FP64 and mixed)
 };
 
 #define RGF_FWD_ENTRY(NW, S, C)                                              \
@@ -87,27 +130,33 @@ struct FwdEntry {
         {rgf_fwd_kernel<double, false, NW, S, C>,                            \
          rgf_fwd_kernel<float, true, NW, S, C>,                              \
          rgf_fwd_kernel<float, false, NW, S, C>},                            \
-        rgf_fwd_kernel<double, false, NW, S, C, true>                        \
+        rgf_fwd_kernel<double, false, NW, S, C, true>, false                 \
   }
 
 const FwdEntry kFwd[] = {
     RGF_FWD_ENTRY(1, 1, 8),  RGF_FWD_ENTRY(1, 1, 16), RGF_FWD_ENTRY(2, 1, 16),
     RGF_FWD_ENTRY(4, 1, 12), RGF_FWD_ENTRY(4, 1, 15), RGF_FWD_ENTRY(4, 1, 16),
     RGF_FWD_ENTRY(8, 1, 8),  RGF_FWD_ENTRY(8, 2, 12), RGF_FWD_ENTRY(8, 2, 15), RGF_FWD_ENTRY(8, 2, 16),
+    // matrix-core Gauss-Jordan for 96 < n <= 128 (the FP32 study mode and the
+    // per-channel transmission keep the register tiling's kernels)
+    {8, 2, 16,
+     {rgf_fwd_mgj_kernel<double, false>, rgf_fwd_mgj_kernel<float, true>,
+      rgf_fwd_kernel<float, false, 8, 2, 16>},
+     rgf_fwd_kernel<double, false, 8, 2, 16, true>, true},
 };
 
 }  // namespace
 
 int slot_matrices(int precision, bool grad) {
-  // forward: K, G1, residual/trace scratch (+ second K when refining);
-  // adjoint adds Z, Q and one more scratch
+  // forward: K, G1, residual/trace scratch (+ second K and M_h when
+  // refining); adjoint adds Z, Q and one more scratch
   if (grad) return 7;
-  return precision == RGF_PREC_MIXED ? 4 : 3;
+  return precision == RGF_PREC_MIXED ? 5 : 3;
 }
 
 int tile_count() { return (int)(sizeof(kFwd) / sizeof(kFwd[0])); }
 
-TileCfg tile_at(int i) { return TileCfg{i, kFwd[i].NW, kFwd[i].S, kFwd[i].C}; }
+TileCfg tile_at(int i) { return TileCfg{i, kFwd[i].NW, kFwd[i].S, kFwd[i].C, kFwd[i].mgj}; }
 
 bool pick_tile(int n, int precision, TileCfg* out) {
   int tid = 0, per_cu = 0;
@@ -115,10 +164,15 @@ bool pick_tile(int n, int precision, TileCfg* out) {
     *out = tile_at(tid);
     return true;
   }
+  // mixed precision above 96 rows: the matrix-core Gauss-Jordan in FP32 (it
+  // pads to 128 rows); FP64 and the FP32 study keep the smallest register
+  // tiling that holds n (in FP64 the register elimination is faster: the
+  // blocked version's serial panel eliminations set its pace)
+  const bool mgj = n > 96 && n <= kTileMaxRows && precision == RGF_PREC_MIXED;
   for (int i = 0; i < (int)(sizeof(kFwd) / sizeof(kFwd[0])); ++i) {
     const FwdEntry& f = kFwd[i];
-    if (f.NW * f.C >= n && 64 * f.S >= f.NW * f.C) {
-      *out = TileCfg{i, f.NW, f.S, f.C};
+    if (f.mgj == mgj && f.NW * f.C >= n && 64 * f.S >= f.NW * f.C) {
+      *out = tile_at(i);
       return true;
     }
   }

@@ -15,6 +15,7 @@ namespace rgf {
 struct TileCfg {
   int id;  // index into the kernel table of a launcher
   int NW, S, C;
+  bool mgj = false;  // forward sweep with the matrix-core Gauss-Jordan (same NW, S, C)
   int NP() const { return NW * C; }
   int threads() const { return NW * 64; }
 };

@@ -26,6 +26,7 @@
 #include "rgf_engine.hpp"
 #include "rgf_internal.hpp"
 #include "rgf_mfma.hpp"
+#include "rgf_mgj.hpp"
 
 namespace rgf {
 
@@ -422,6 +423,226 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
   if (h > 0) {
     // G1_h = (G1_{h-1} C_{h-1}) g_h on the matrix cores; g_h is complex
     // symmetric, so it is read transposed (rows contiguous)
+    const double t = a.t;
+    const cx<double>* G1r = opaque_uniform(G1in);
+    const cx<double>* Kg = opaque_uniform(Kout);
+    cx<double>* G1w = opaque_uniform(G1out);
+    auto fb = [&](int k, int c) -> cx<double> { return ldg(Kg + (size_t)k * NP + c); };
+    auto epi = [&](int r, int c, cx<double> v, bool ok) {
+      if (ok) stg(G1w + (size_t)c * NP + r, v);
+    };
+    if (!(h & 1)) {
+      auto fa = [&](int r, int k) -> cx<double> {
+        return cscale(ldg(G1r + (size_t)k * NP + r), t);
+      };
+      gemm_mfma<NW, NP>(n1, n, n, fa, fb, epi);
+    } else {
+      const int nL = half_size(a.N, e ^ 1);
+      auto fa = [&](int r, int k) -> cx<double> {
+        const int k0 = nb_lo(k, e), k1 = nb_hi(k, e);
+        cx<double> acc = mk(0.0, 0.0);
+        if (k0 >= 0) acc = ldg(G1r + (size_t)k0 * NP + r);
+        if (k1 < nL) acc = cadd(acc, ldg(G1r + (size_t)k1 * NP + r));
+        return cscale(acc, t);
+      };
+      gemm_mfma<NW, NP>(n1, n, n, fa, fb, epi);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// The half-slice step with the matrix-core inversion of rgf_mgj.hpp (8
+// waves, n <= 128; the G1 product and the refinement on the matrix cores).
+
+// M_h in the accumulator layout of wave w's tile column (rgf_mgj.hpp),
+// padded with the identity; every entry is formed in FP64 and rounded once
+// to T. K (g of the previous half-slice) is complex symmetric, so entry
+// (r, c) reads K[r][c] with the 16 lanes of a row group on 16 consecutive
+// columns (coalesced). Returns (wave-uniform) the high word of
+// max_k |E - eps_{h,k}|, for the accuracy guard.
+// If Mout is non-null, M_h is also stored there in FP64, row-major
+// (Mout[r NP + c]; M_h is complex symmetric, so it reads column-major too).
+template <typename T>
+__device__ __forceinline__ uint32_t mgj_build(MgjTile<T>& D, const SweepArgs& a, const Tuple& q,
+                                              int h, const cx<double>* K,
+                                              cx<double>* Mout = nullptr) {
+  constexpr int NP = MG_NP;
+  // lane and wave made opaque so that the per-entry row / column offsets
+  // are recomputed here instead of being hoisted out of the slice loop
+  // (32 entries x up to four offsets would stay live for the whole sweep)
+  int lane = lane_id(), w = wave_id();
+  asm volatile("" : "+v"(lane));
+  asm volatile("" : "+s"(w));
+  const int li = lane & 15, lk = lane >> 4;
+  const bool rhalf = (h & 1) != 0;
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  const int nL = half_size(a.N, e ^ 1);
+  const double mt2 = -(a.t * a.t);
+  const double* eps_slice = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
+  const double* ph = (h == 0) ? a.phi : (h == 2 * a.L - 1) ? a.phi + (size_t)a.P * NP : nullptr;
+  K = opaque_uniform(K);
+  const int c = 16 * w + li;
+  const int c0 = nb_lo(c, e), c1 = nb_hi(c, e);
+  uint32_t dk = 0u;
+#pragma unroll
+  for (int I = 0; I < MG_TI; ++I)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * I + mgj_row<T>(v, lk);
+      cx<double> x = mk((r == c) ? 1.0 : 0.0, 0.0);
+      if (r < n && c < n) {
+        x = mk(0.0, 0.0);
+        if (h > 0) {
+          if (!rhalf) {
+            x = cscale(ldg(K + (size_t)r * NP + c), mt2);
+          } else {
+            const int r0 = nb_lo(r, e), r1 = nb_hi(r, e);
+            cx<double> acc = mk(0.0, 0.0);
+            if (r0 >= 0) {
+              if (c0 >= 0) acc = cadd(acc, ldg(K + (size_t)r0 * NP + c0));
+              if (c1 < nL) acc = cadd(acc, ldg(K + (size_t)r0 * NP + c1));
+            }
+            if (r1 < nL) {
+              if (c0 >= 0) acc = cadd(acc, ldg(K + (size_t)r1 * NP + c0));
+              if (c1 < nL) acc = cadd(acc, ldg(K + (size_t)r1 * NP + c1));
+            }
+            x = cscale(acc, mt2);
+          }
+        }
+        if (r == c) {
+          const double d = q.z.re - (eps_slice ? eps_slice[half_row(r, e)] : 0.0);
+          dk = max(dk, mag_hi(fabs(d)));
+          x = cadd(x, mk(d, q.z.im));
+        }
+        if (ph) {  // lead self-energy on the first and the last half-slice
+          for (int p = 0; p < a.P; ++p) {
+            const double f = ph[(size_t)p * NP + r] * ph[(size_t)p * NP + c];
+            x.re = fma(-f, q.sig[p].re, x.re);
+            x.im = fma(-f, q.sig[p].im, x.im);
+          }
+        }
+      }
+      mgj_set(D, I, v, mk<T>((T)x.re, (T)x.im));
+      if (Mout) stg(Mout + (size_t)r * NP + c, x);
+      // bound the loads in flight (register pressure)
+      if ((v & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+  return wave_max_u32(dk);
+}
+
+// g = M_h^{-1} into Kout by the matrix-core Gauss-Jordan in precision T
+// (and into K2 if non-null); records kappa_h for the guard in sm.kred.
+template <typename T, int NW, int S, int C>
+__device__ __forceinline__ uint32_t mgj_inverse_to(const SweepArgs& a, const Tuple& q, int h,
+                                                   const cx<double>* Kprev, cx<double>* Kout,
+                                                   cx<double>* K2, SweepSmem<NW, S, C>& sm,
+                                                   MgjSmem<T>& ms, cx<double>* Mout = nullptr) {
+  constexpr bool F64 = sizeof(T) == sizeof(double);
+  const int n = half_size(a.N, half_parity(h, a.parity));
+  MgjTile<T> D;
+  const uint32_t dkey = mgj_build<T>(D, a, q, h, Kprev, Mout);
+  const double f = mgj_pow2_scale(mgj_absmax(D, ms), F64 ? -1022 : -126);
+  mgj_scale(D, (T)f);
+  mgj_invert(D, n, ms, &sm.flag);
+  {
+    uint32_t b = 0u;
+#pragma unroll
+    for (int I = 0; I < MG_TI; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b = max(b, mag_hi(cabs1(mgj_get(D, I, v))));
+    b = wave_max_u32(b);
+    if (lane_id() == 0)
+      sm.kred[wave_id()] = F64 ? __longlong_as_double((long long)((uint64_t)b << 32))
+                               : (double)__uint_as_float(b);
+  }
+  mgj_store<T, double>(D, n, f, ms, Kout, K2);
+  return dkey;
+}
+
+template <typename TJ, bool REFINE>
+__device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q, int h,
+                                              const cx<double>* Kprev, cx<double>* Kout,
+                                              const cx<double>* G1in, cx<double>* G1out,
+                                              cx<double>* Rbuf, cx<double>* Mbuf,
+                                              SweepSmem<8, 2, 16>& sm, MgjSmem<double>& ms64) {
+  constexpr int NW = 8, NP = MG_NP;
+  static_assert(NP == 8 * 16, "matrix-core tile is the (8, 2, 16) tiling");
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  uint32_t dkey;
+  if constexpr (sizeof(TJ) == sizeof(double))
+    dkey = mgj_inverse_to<double>(a, q, h, Kprev, Kout, h == 0 ? G1out : nullptr, sm, ms64);
+  else
+    dkey = mgj_inverse_to<float>(a, q, h, Kprev, Kout, (h == 0 && !REFINE) ? G1out : nullptr, sm,
+                                 *reinterpret_cast<MgjSmem<float>*>(&ms64),
+                                 REFINE ? Mbuf : nullptr);
+  __syncthreads();
+  if (threadIdx.x == 0) {  // kred is written again only after further barriers
+    double km = sm.kred[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) km = max(km, sm.kred[i]);
+    sm.ksum += km;
+    if (dkey < mag_hi(kChiralWindow * fabs(a.t))) sm.ksum_c += km;
+  }
+  if constexpr (REFINE) {
+    // Newton's iteration in FP64 on the matrix cores from the FP32 start:
+    //   R_k = I - M g_k,  g_{k+1} = g_k (I + R_k);
+    // the start is used only if n max|R_0| < 1/2 (the infinity norm bound
+    // keeps the spectral radius of R_0 below 1), the residual must shrink
+    // at every step and converge within four; otherwise the half-slice is
+    // inverted again by the FP64 Gauss-Jordan.
+    bool converged = false;
+    double rprev = 0.0;
+    for (int it = 0; it < 4; ++it) {
+      double lmax = 0.0;
+      {
+        // M_h as stored by the build (FP64, complex symmetric)
+        auto fa = [&](int r, int k) -> cx<double> { return ldg(Mbuf + (size_t)k * NP + r); };
+        auto fb = [&](int k, int c) -> cx<double> { return ldg(Kout + (size_t)c * NP + k); };
+        auto epi = [&](int r, int c, cx<double> v, bool ok) {
+          if (!ok) return;
+          const cx<double> d = mk(((r == c) ? 1.0 : 0.0) - v.re, -v.im);
+          const double m1 = cabs1(d);
+          lmax = (m1 > lmax || m1 != m1) ? m1 : lmax;
+          stg(Rbuf + (size_t)c * NP + r, mk(((r == c) ? 1.0 : 0.0) + d.re, d.im));  // I + R_k
+        };
+        gemm_mfma<NW, NP>(n, n, n, fa, fb, epi);
+      }
+      const double rmax = block_max<NW>(lmax, sm.red);
+      if (it == 0 ? !((double)n * rmax < 0.5) : !(rmax < rprev)) break;  // not converging
+      if (!(rmax > 1e-15)) {  // at rounding level already
+        converged = true;
+        break;
+      }
+      {
+        auto fa = [&](int r, int k) -> cx<double> { return ldg(Kout + (size_t)k * NP + r); };
+        auto fb = [&](int k, int c) -> cx<double> { return ldg(Rbuf + (size_t)c * NP + k); };
+        auto epi = [&](int r, int c, cx<double> v, bool ok) {
+          if (ok) stg(Kout + (size_t)c * NP + r, v);
+        };
+        gemm_mfma<NW, NP>(n, n, n, fa, fb, epi);
+      }
+      __syncthreads();
+      if (rmax < 1e-8) {  // the next residual is below n rmax^2 < n * 1e-16
+        converged = true;
+        break;
+      }
+      rprev = rmax;
+    }
+    if (!converged) {
+      (void)mgj_inverse_to<double>(a, q, h, Kprev, Kout, nullptr, sm, ms64);
+      __syncthreads();
+    }
+    if (h == 0) {
+      for (int i = threadIdx.x; i < NP * NP; i += NW * 64) stg(G1out + i, ldg(Kout + i));
+      __syncthreads();
+    }
+  }
+  if (h > 0) {
+    // G1_h = (G1_{h-1} C_{h-1}) g_h on the matrix cores (g_h read transposed)
     const double t = a.t;
     const cx<double>* G1r = opaque_uniform(G1in);
     const cx<double>* Kg = opaque_uniform(Kout);

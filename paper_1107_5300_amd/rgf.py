@@ -385,7 +385,18 @@ def autotune(ribbon, precision="fp64", device=None):
     _L.check(L.rgf_autotune(ctypes.byref(d), prec, _vp(ws), ws.numel(), _stream(),
                             ctypes.byref(chosen)))
     c = chosen.value
-    return c // 10000, (c // 1000) % 10, (c // 10) % 100, c % 10
+    return TileChoice(c % 100000 // 10000, (c // 1000) % 10, (c // 10) % 100, c % 10,
+                      mgj=c >= 100000)
+
+
+class TileChoice(tuple):
+    """(NW, S, C, slots_per_cu) of the autotuner's choice; .mgj is True for
+    the forward sweep with the matrix-core Gauss-Jordan."""
+
+    def __new__(cls, NW, S, C, per_cu, mgj=False):
+        t = super().__new__(cls, (NW, S, C, per_cu))
+        t.mgj = bool(mgj)
+        return t
 
 
 def version():

@@ -296,7 +296,9 @@ def test_batched_graph_capture_replays(P):
 
 def test_autotune_choice_and_result(P):
     """The autotuner picks a tiling that holds the width; results with the
-    tuned choice equal the default ones."""
+    tuned choice equal the default ones to rounding (the choice may switch
+    between the register tiling and the matrix-core Gauss-Jordan, whose
+    elimination orders differ)."""
     import torch
     for N in (60, 240):
         _say("autotune", N)
@@ -307,5 +309,5 @@ def test_autotune_choice_and_result(P):
         NW, S, C, per_cu = P.autotune(rib)
         assert NW * C >= (N + 1) // 2 and 64 * S >= NW * C and per_cu in (0, 1)
         after = _gpu_T(P, N, 6, 0, W.T_HOP, Es, eps[None])
-        assert np.abs(before - after).max() <= 1e-13
+        assert np.abs(before - after).max() <= 1e-12 * max(1.0, np.abs(before).max())
         torch.cuda.synchronize()
