@@ -143,6 +143,47 @@ def build(verbose=False, jobs=None, incremental=False):
     return LIB
 
 
+def build_abi_check(verbose=False):
+    """_build/abi_check: the host validation layer (rgf_api.cpp,
+    rgf_noalloc.hip) rebuilt with AddressSanitizer and UndefinedBehavior-
+    Sanitizer on the host side only, linked with the other objects of the
+    normal build and driven by csrc/abi_check.cpp. Runs without a GPU.
+    Returns the executable's path."""
+    cc = hipcc()
+    objdir = os.path.join(HERE, "_build")
+    asan_dir = os.path.join(objdir, "asan")
+    os.makedirs(asan_dir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        if src in ("rgf_api.cpp", "rgf_noalloc.hip"):
+            obj = os.path.join(asan_dir, os.path.splitext(src)[0] + ".o")
+            cmd = [cc] + (["-x", "hip"] if src.endswith(".cpp") else []) + HIP_FLAGS + san + \
+                  ["-c", os.path.join(CSRC, src), "-o", obj]
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+            if r.returncode != 0:
+                raise RuntimeError("sanitizer build failed:\n" + r.stdout.decode(errors="replace"))
+        elif not os.path.exists(obj):
+            raise RuntimeError(f"{obj} missing: run build() first")
+        objs.append(obj)
+    exe = os.path.join(asan_dir, "abi_check")
+    drv = os.path.join(asan_dir, "abi_check.o")
+    r = subprocess.run([cc, "-x", "hip", "--offload-arch=gfx950", "-O1", "-std=c++17"] + san +
+                       ["-c", os.path.join(CSRC, "abi_check.cpp"), "-o", drv],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("sanitizer driver build failed:\n" + r.stdout.decode(errors="replace"))
+    r = subprocess.run([cc, "--offload-arch=gfx950"] + san + ["-o", exe, drv] + objs,
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("sanitizer link failed:\n" + r.stdout.decode(errors="replace"))
+    if verbose:
+        print(exe)
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(LIB)

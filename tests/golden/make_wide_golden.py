@@ -2,8 +2,9 @@
 tests/golden/ (wide_ribbons.txt, large_n480_sampled.txt, wide_grad.txt,
 wide_ldos.txt).
 
-The oracle's dense lead decimation costs about two minutes per energy at
-N = 480 and its sweep about five minutes for L = 8000, too slow to run inside
+The oracle's lead self-energies (the Bloch-mode eigenproblem of the
+960-site lead cell) take tens of seconds per energy at N = 480 and its sweep
+about five minutes for L = 8000, too slow to run inside
 the GPU tests, so these values are written once, by this script, from
 oracle/ and the seeded input generators only. Each line names its ribbon,
 disorder realization and energy; the disorder is regenerated from the seed

@@ -246,3 +246,25 @@ def test_autotune_wide_widths():
     for prec in (1, 2):
         assert lib.rgf_autotune_workspace_bytes(ctypes.byref(d), prec) == 0
         assert b"FP64 only" in lib.rgf_last_error_message()
+
+
+def test_validation_layer_under_sanitizers():
+    """The host validation and planning code (rgf_api.cpp, rgf_noalloc.hip)
+    rebuilt with AddressSanitizer and UndefinedBehaviorSanitizer on the host
+    side and driven through every entry point's error and planning paths by
+    csrc/abi_check.cpp (no GPU needed). Leak checking is off: the HIP
+    runtime keeps allocations until exit."""
+    import shutil
+    import subprocess
+    if shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("hipcc not available")
+    from paper_1107_5300_amd import build as B
+    exe = B.build_abi_check()
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, env=env,
+                       timeout=300)
+    out = r.stdout.decode(errors="replace")
+    assert r.returncode == 0, out[-3000:]
+    assert "abi_check: ok" in out
+    assert "runtime error" not in out and "AddressSanitizer" not in out
