@@ -221,11 +221,47 @@ def _gamma(sig):
 # --------------------------------------------------------------------------
 
 def _device_slices(N, L, t, eps):
+    """Slice Hamiltonians H_1..H_L; a vacant site (on-site energy +inf, see
+    _vacancies) gets 0 here, its row and column are decoupled by
+    _slice_inverse."""
     if eps is None:
         eps = np.zeros((L, N))
     eps = np.asarray(eps, dtype=np.float64)
     assert eps.shape == (L, N)
+    eps = np.where(np.isposinf(eps), 0.0, eps)
     return [slice_hamiltonian(N, t, eps[i]) for i in range(L)]
+
+
+# --------------------------------------------------------------------------
+# Lattice defects (the paper's simulation flow starts from generating atomic
+# defects; its model paragraph names lattice defects beside disorder). A
+# vacancy removes an atom: on-site energy +inf, the limit in which the site
+# decouples from every bond and from the leads.
+# --------------------------------------------------------------------------
+
+def _vacancies(N, L, eps):
+    """Boolean [L, N]: the sites removed from the lattice (eps = +inf)."""
+    if eps is None:
+        return np.zeros((L, N), dtype=bool)
+    return np.isposinf(np.asarray(eps, dtype=np.float64))
+
+
+def _slice_inverse(A, vac):
+    """A^{-1} for the lattice without the vacant sites (boolean mask vac):
+    their rows and columns of A are replaced by the identity's, so the
+    inverse is block diagonal, and their own diagonal entries are then set
+    to zero -- the Green's function of the lattice with the sites removed,
+    embedded with zero rows and columns."""
+    if vac is None or not vac.any():
+        return np.linalg.inv(A)
+    idx = np.nonzero(vac)[0]
+    A = A.copy()
+    A[idx, :] = 0.0
+    A[:, idx] = 0.0
+    A[idx, idx] = 1.0
+    g = np.linalg.inv(A)
+    g[idx, idx] = 0.0
+    return g
 
 
 def transmission(N, L, t, eta, E, eps=None, parity=0, sigmas=None,
@@ -236,12 +272,13 @@ def transmission(N, L, t, eta, E, eps=None, parity=0, sigmas=None,
         sigmas = lead_self_energies(N, L, t, eta, E, parity)
     sig_l, sig_r = sigmas
     Hs = _device_slices(N, L, t, eps)
+    vac = _vacancies(N, L, eps)
     eye = np.eye(N, dtype=np.complex128)
     # slice 1
     A = z * eye - Hs[0] - sig_l
     if L == 1:
         A = A - sig_r
-    g = np.linalg.inv(A)
+    g = _slice_inverse(A, vac[0])
     G1 = g
     for j in range(2, L + 1):
         u = coupling_diag(N, t, j - 1, parity)     # H_{j-1,j} = diag(u)
@@ -249,7 +286,7 @@ def transmission(N, L, t, eta, E, eps=None, parity=0, sigmas=None,
         A = z * eye - Hs[j - 1] - u[:, None] * g * u[None, :]
         if j == L:
             A = A - sig_r
-        g = np.linalg.inv(A)
+        g = _slice_inverse(A, vac[j - 1])
         G1 = (G1 * u[None, :]) @ g
     T = np.real(np.trace(_gamma(sig_l) @ G1 @ _gamma(sig_r) @ G1.conj().T))
     if return_g:
@@ -268,18 +305,19 @@ def transmission_rl(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
         sigmas = lead_self_energies(N, L, t, eta, E, parity)
     sig_l, sig_r = sigmas
     Hs = _device_slices(N, L, t, eps)
+    vac = _vacancies(N, L, eps)
     eye = np.eye(N, dtype=np.complex128)
     A = z * eye - Hs[L - 1] - sig_r
     if L == 1:
         A = A - sig_l
-    g = np.linalg.inv(A)
+    g = _slice_inverse(A, vac[L - 1])
     GL = g                                       # G_{L,j} (right-connected)
     for j in range(L - 1, 0, -1):
         U = coupling(N, t, j, parity)            # H_{j,j+1}
         A = z * eye - Hs[j - 1] - U @ g @ U.T
         if j == 1:
             A = A - sig_l
-        g = np.linalg.inv(A)
+        g = _slice_inverse(A, vac[j - 1])
         GL = GL @ U.T @ g
     return np.real(np.trace(_gamma(sig_r) @ GL @ _gamma(sig_l) @ GL.conj().T))
 
@@ -302,13 +340,24 @@ def _full_matrix(N, L, t, eta, E, eps, parity, sigmas):
 
 
 def transmission_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
-    """Brute force: invert the full device matrix, then Eq. (2)."""
+    """Brute force: invert the full device matrix, then Eq. (2). Vacant
+    sites (eps = +inf) are deleted from the matrix, and from the lead
+    couplings, before the inversion."""
     if sigmas is None:
         sigmas = lead_self_energies(N, L, t, eta, E, parity)
     sig_l, sig_r = sigmas
-    G = np.linalg.inv(_full_matrix(N, L, t, eta, E, eps, parity, sigmas))
-    G1L = G[:N, (L - 1) * N:]
-    return np.real(np.trace(_gamma(sig_l) @ G1L @ _gamma(sig_r) @ G1L.conj().T))
+    M = _full_matrix(N, L, t, eta, E, eps, parity, sigmas)
+    keep = ~_vacancies(N, L, eps).reshape(-1)
+    first, last = keep.copy(), keep.copy()
+    first[N:] = False                      # kept sites of slice 1
+    last[:(L - 1) * N] = False             # kept sites of slice L
+    G = np.linalg.inv(M[np.ix_(keep, keep)])
+    cols = np.cumsum(keep) - 1             # position of a kept site in G
+    G1L = G[np.ix_(cols[first], cols[last])]
+    kl, kr = first[:N], last[(L - 1) * N:]
+    gl = _gamma(sig_l)[np.ix_(kl, kl)]
+    gr = _gamma(sig_r)[np.ix_(kr, kr)]
+    return np.real(np.trace(gl @ G1L @ gr @ G1L.conj().T))
 
 
 # --------------------------------------------------------------------------
@@ -318,19 +367,35 @@ def transmission_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
 #   dT/d eps_s = 2 Re[ G[s, slice L] B G[slice 1, s] ],  B = Gamma_R G_1L^dag Gamma_L.
 # --------------------------------------------------------------------------
 
+def _kept_inverse(N, L, t, eta, E, eps, parity, sigmas):
+    """(G over the kept sites, kept mask [L*N], position of each kept site
+    in G): the full device matrix with vacant sites deleted, inverted."""
+    M = _full_matrix(N, L, t, eta, E, eps, parity, sigmas)
+    keep = ~_vacancies(N, L, eps).reshape(-1)
+    return np.linalg.inv(M[np.ix_(keep, keep)]), keep, np.cumsum(keep) - 1
+
+
 def transmission_grad_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
-    """(T, dT/deps [L, N]) from the full inverse (tiny ribbons only)."""
+    """(T, dT/deps [L, N]) from the full inverse (tiny ribbons only); vacant
+    sites are deleted and get a zero derivative."""
     if sigmas is None:
         sigmas = lead_self_energies(N, L, t, eta, E, parity)
     sig_l, sig_r = sigmas
-    G = np.linalg.inv(_full_matrix(N, L, t, eta, E, eps, parity, sigmas))
-    G1L = G[:N, (L - 1) * N:]
-    gl, gr = _gamma(sig_l), _gamma(sig_r)
+    G, keep, pos = _kept_inverse(N, L, t, eta, E, eps, parity, sigmas)
+    first = keep.copy()
+    first[N:] = False
+    last = keep.copy()
+    last[:(L - 1) * N] = False
+    kl, kr = first[:N], last[(L - 1) * N:]
+    G1L = G[np.ix_(pos[first], pos[last])]
+    gl = _gamma(sig_l)[np.ix_(kl, kl)]
+    gr = _gamma(sig_r)[np.ix_(kr, kr)]
     T = np.real(np.trace(gl @ G1L @ gr @ G1L.conj().T))
     B = gr @ G1L.conj().T @ gl
-    right = G[:, (L - 1) * N:]       # G[s, slice L]
-    left = G[:N, :]                  # G[slice 1, s]
-    d = 2.0 * np.real(np.einsum("sa,ab,bs->s", right, B, left))
+    right = G[:, pos[last]]          # G[s, slice L]
+    left = G[pos[first], :]          # G[slice 1, s]
+    d = np.zeros(N * L)
+    d[keep] = 2.0 * np.real(np.einsum("sa,ab,bs->s", right, B, left))
     return T, d.reshape(L, N)
 
 
@@ -350,12 +415,13 @@ def transmission_grad(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
         sigmas = lead_self_energies(N, L, t, eta, E, parity)
     sig_l, sig_r = sigmas
     Hs = _device_slices(N, L, t, eps)
+    vac = _vacancies(N, L, eps)
     eye = np.eye(N, dtype=np.complex128)
     gs, G1s = [], []
     A = z * eye - Hs[0] - sig_l
     if L == 1:
         A = A - sig_r
-    g = np.linalg.inv(A)
+    g = _slice_inverse(A, vac[0])
     gs.append(g)
     G1s.append(g)
     for j in range(2, L + 1):
@@ -363,7 +429,7 @@ def transmission_grad(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
         A = z * eye - Hs[j - 1] - U.T @ g @ U
         if j == L:
             A = A - sig_r
-        g = np.linalg.inv(A)
+        g = _slice_inverse(A, vac[j - 1])
         gs.append(g)
         G1s.append(G1s[-1] @ U @ g)
     G1L = G1s[-1]
@@ -390,11 +456,14 @@ def transmission_grad(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
 # --------------------------------------------------------------------------
 
 def ldos_bf(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
-    """-Im diag(G) / pi as [L, N], from the full inverse (tiny ribbons only)."""
+    """-Im diag(G) / pi as [L, N], from the full inverse (tiny ribbons only);
+    vacant sites are deleted and get zero."""
     if sigmas is None:
         sigmas = lead_self_energies(N, L, t, eta, E, parity)
-    G = np.linalg.inv(_full_matrix(N, L, t, eta, E, eps, parity, sigmas))
-    return (-np.imag(np.diag(G)) / np.pi).reshape(L, N)
+    G, keep, _ = _kept_inverse(N, L, t, eta, E, eps, parity, sigmas)
+    out = np.zeros(N * L)
+    out[keep] = -np.imag(np.diag(G)) / np.pi
+    return out.reshape(L, N)
 
 
 def ldos(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
@@ -409,19 +478,20 @@ def ldos(N, L, t, eta, E, eps=None, parity=0, sigmas=None):
         sigmas = lead_self_energies(N, L, t, eta, E, parity)
     sig_l, sig_r = sigmas
     Hs = _device_slices(N, L, t, eps)
+    vac = _vacancies(N, L, eps)
     eye = np.eye(N, dtype=np.complex128)
     gs = []
     A = z * eye - Hs[0] - sig_l
     if L == 1:
         A = A - sig_r
-    g = np.linalg.inv(A)
+    g = _slice_inverse(A, vac[0])
     gs.append(g)
     for j in range(2, L + 1):
         U = coupling(N, t, j - 1, parity)
         A = z * eye - Hs[j - 1] - U.T @ g @ U
         if j == L:
             A = A - sig_r
-        g = np.linalg.inv(A)
+        g = _slice_inverse(A, vac[j - 1])
         gs.append(g)
     out = np.empty((L, N))
     F = gs[-1]

@@ -79,6 +79,23 @@ def disorder_batch(L, N, w, n_real, t=T_HOP):
     return np.stack([disorder(L, N, w, r, t) for r in range(n_real)])
 
 
+def vacancies(eps, density, seed, rows=None):
+    """eps with a seeded random fraction `density` of its sites removed
+    (on-site energy +inf, the library's vacancy marker). rows: the
+    transverse rows eligible (all if None); rows=(0, N-1) gives edge
+    roughness. Returns a new float64 array."""
+    eps = np.array(eps, dtype=np.float64, copy=True)
+    L, N = eps.shape
+    rng = np.random.default_rng(SEED_BASE + 7919 * (seed + 1))
+    mask = rng.random((L, N)) < density
+    if rows is not None:
+        keep = np.zeros(N, dtype=bool)
+        keep[list(rows)] = True
+        mask &= keep[None, :]
+    eps[mask] = np.inf
+    return eps
+
+
 def fd_sites(L, N, count=100, seed=4):
     """Sites (i, k) for finite-difference gradient checks, without replacement."""
     rng = np.random.default_rng(seed)
