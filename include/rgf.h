@@ -49,7 +49,7 @@ extern "C" {
 #endif
 
 #define RGF_ABI_VERSION_MAJOR 1
-#define RGF_ABI_VERSION_MINOR 2
+#define RGF_ABI_VERSION_MINOR 3
 
 /* Ribbon geometry and model constants. */
 typedef struct {
@@ -124,7 +124,12 @@ size_t rgf_workspace_bytes(const rgf_ribbon_desc* desc, int64_t n_energies,
 /* Conductance T[r][e] (Eq. (2)) for every realization r and energy e.
  *   energies_ev   [n_energies]
  *   onsite_eps_ev [n_real][L][N], or NULL for pristine ribbons (then n_real
- *                 is the number of identical output rows)
+ *                 is the number of identical output rows). An entry of
+ *                 +inf removes that atom (a vacancy: the site decouples
+ *                 from its bonds and the leads, the limit eps -> +inf);
+ *                 every entry point accepts it, and the gradient and LDOS
+ *                 at a vacancy are 0. Other non-finite entries (NaN,
+ *                 -inf) are not supported and are not checked.
  *   T_out         [n_real][n_energies]
  *   status_out    [n_real][n_energies] int32, or NULL
  * The recursion follows Eqs. (4)-(5); the lead self-energies (method

@@ -133,6 +133,15 @@ __device__ __host__ __forceinline__ int half_size(int N, int e) {
 
 __device__ __host__ __forceinline__ int half_row(int a, int e) { return 2 * a + e; }
 
+// A vacancy (a site removed from the lattice) is marked by the on-site
+// energy +inf: that limit decouples the site, so its row and column of
+// every Green's function vanish and the rest is that of the lattice without
+// it. The kernels replace its row and column of M by the identity's and
+// zero its diagonal entry of g.
+__device__ __host__ __forceinline__ bool is_vacancy(double eps) {
+  return eps == __builtin_huge_val();
+}
+
 // Neighbours in L_i of row b of R_i (R_i parity eR): local a = b - 1 + eR and
 // a = b + eR, each valid only inside [0, nL).
 __device__ __forceinline__ int nb_lo(int b, int eR) { return b - 1 + eR; }

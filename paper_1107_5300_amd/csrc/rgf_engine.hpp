@@ -332,11 +332,15 @@ __device__ __forceinline__ void scale_regs(cx<T> (&A)[S][C], T f) {
 // scratch and stores whole columns coalesced. Columns/rows >= n are skipped.
 // Every entry is multiplied by f (the scale of the inversion; a power of
 // two). If K2 is non-null the same matrix is also written there.
+// veps (optional): on-site energies of the matrix's rows, row a at
+// veps[2 a + e]; the diagonal entry of a vacancy (+inf, whose row and column
+// of the inverted matrix were the identity's) is stored as 0.
 template <typename T, typename TG, int NW, int S, int C>
 __device__ __forceinline__ void store_unpermuted(const cx<T> (&X)[S][C], int n, T f,
                                                  cx<T>* wbuf_all, const int* pivrow,
                                                  const int* pinv, cx<TG>* K,
-                                                 cx<TG>* K2) {
+                                                 cx<TG>* K2, const double* veps = nullptr,
+                                                 int e = 0) {
   constexpr int NP = NW * C;
   const int lane = lane_id(), w = wave_id();
   cx<T>* wbuf = wbuf_all + w * NP;
@@ -353,12 +357,14 @@ __device__ __forceinline__ void store_unpermuted(const cx<T> (&X)[S][C], int n, 
     }
     wave_sync_lds();
     const int col = pivrow[c];
+    const bool vcol = veps && is_vacancy(veps[half_row(col, e)]);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int r = lane + 64 * s;
       if (r < n) {
         cx<T> v = wbuf[r];
         cx<TG> g = mk<TG>((TG)(v.re * f), (TG)(v.im * f));
+        if (vcol && r == col) g = mk<TG>(TG(0), TG(0));
         stg(K + (size_t)col * NP + r, g);
         if (K2) stg(K2 + (size_t)col * NP + r, g);
       }

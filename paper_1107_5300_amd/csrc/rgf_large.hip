@@ -194,7 +194,8 @@ __device__ __forceinline__ void pgj_panel(cx<double> (&A)[RS][RC], int nsteps, i
 
 // M_h (n x n) into X, column-major; returns the largest |re| + |im| of the
 // thread's entries (NaN if any is NaN) and, in dmax, the largest
-// |E - eps_{h,k}| of the thread's diagonal entries (for the accuracy guard).
+// |E - eps_{h,k}| of the thread's diagonal entries (for the accuracy guard;
+// vacancies left out).
 __device__ __forceinline__ double build_M_large(const SweepArgs& a, const Tuple& q, int h,
                                                 const cx<double>* K, cx<double>* X,
                                                 double& dmax) {
@@ -229,7 +230,7 @@ __device__ __forceinline__ double build_M_large(const SweepArgs& a, const Tuple&
     }
     if (r == c) {
       const double d = q.z.re - (eps ? eps[half_row(r, e)] : 0.0);
-      dmax = fmax(dmax, fabs(d));
+      if (!isinf(d)) dmax = fmax(dmax, fabs(d));  // vacancies left out
       v = cadd(v, mk(d, q.z.im));
     }
     if (ph) {  // lead self-energy on the first and the last half-slice
@@ -239,6 +240,9 @@ __device__ __forceinline__ double build_M_large(const SweepArgs& a, const Tuple&
         v.im = fma(-f, q.sig[p].im, v.im);
       }
     }
+    // a vacancy's row and column are the identity's
+    if (eps && (is_vacancy(eps[half_row(r, e)]) || is_vacancy(eps[half_row(c, e)])))
+      v = mk((r == c) ? 1.0 : 0.0, 0.0);
     const double m1 = cabs1(v);
     mx = (m1 > mx || m1 != m1) ? m1 : mx;
     stg(X + (size_t)c * LD + r, v);
@@ -258,10 +262,14 @@ __device__ __forceinline__ double pow2_scale(double mx) {
 // (same leading dimension) by the panel Gauss-Jordan; f is the power-of-two
 // scale applied to M for the elimination. Returns (in every thread) kappa =
 // max |(f M)^{-1}|, the condition estimate of the accuracy guard.
+// veps (optional): on-site energies of the rows, row r at veps[vstride r +
+// voff]; the diagonal entry of g at a vacancy (whose row and column of M are
+// the identity's) is stored as 0, the removed site's Green's function.
 template <int RS, int RC, int LDX>
 __device__ __forceinline__ double invert_panels(int n, double f, cx<double>* X, cx<double>* Xp,
                                                 cx<double>* K, cx<double> (&A)[RS][RC],
-                                                LargeSmem& sm) {
+                                                LargeSmem& sm, const double* veps = nullptr,
+                                                int vstride = 1, int voff = 0) {
   constexpr int PBT = BW * RC;
   static_assert(64 * RS <= LDX && PBT * LDX <= BP * BP, "panel tile and staging buffer");
   const int lane = lane_id(), w = wave_id();
@@ -338,7 +346,8 @@ __device__ __forceinline__ double invert_panels(int n, double f, cx<double>* X, 
     const cx<double> x = ldg(X + (size_t)sm.pinv[j] * LDX + sm.pivrow[r]);
     const double m1 = cabs1(x);
     kap = (m1 > kap || m1 != m1) ? m1 : kap;
-    stg(K + (size_t)j * LDX + r, cscale(x, f));
+    const bool vz = veps && r == j && is_vacancy(veps[(size_t)vstride * r + voff]);
+    stg(K + (size_t)j * LDX + r, vz ? mk(0.0, 0.0) : cscale(x, f));
   }
   return block_max<BW>(kap, sm.red);
 }
@@ -358,7 +367,8 @@ __device__ __forceinline__ void large_step(const SweepArgs& a, const Tuple& q, i
   double dmax;
   const double mx = block_max<BW>(build_M_large(a, q, h, Kprev, X, dmax), sm.red);
   dmax = block_max<BW>(dmax, sm.red);
-  const double kap = invert_panels<BS, BC, LD>(n, pow2_scale(mx), X, Xp, Kout, A, sm);
+  const double* veps = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
+  const double kap = invert_panels<BS, BC, LD>(n, pow2_scale(mx), X, Xp, Kout, A, sm, veps, 2, e);
   if (threadIdx.x == 0) {  // read after the next barrier
     sm.ksum += kap;
     if (dmax < kChiralWindow * fabs(a.t)) sm.ksum_c += kap;
@@ -865,6 +875,9 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_ldos_large_kernel(SweepArgs a)
 __device__ __forceinline__ cx<double> m_whole_entry(const SweepArgs& a, const Tuple& q, int i,
                                                     const cx<double>* K, int r, int c) {
   const int eL = half_parity(2 * (i - 1), a.parity);
+  if (q.eps_r && (is_vacancy(q.eps_r[(int64_t)(i - 1) * a.N + r]) ||
+                  is_vacancy(q.eps_r[(int64_t)(i - 1) * a.N + c])))
+    return mk((r == c) ? 1.0 : 0.0, 0.0);  // a vacancy's row and column: the identity's
   cx<double> v = mk(0.0, 0.0);
   if (r == c) v = mk(q.z.re - (q.eps_r ? q.eps_r[(int64_t)(i - 1) * a.N + r] : 0.0), q.z.im);
   if (r == c + 1 || c == r + 1) v.re -= a.t;
@@ -939,7 +952,10 @@ __global__ __launch_bounds__(BW * 64, 2) void rgf_whole_kernel(SweepArgs a) {
     int cur = 0;
     for (int i = 1; i <= a.L; ++i) {
       const double mx = block_max<BW>(build_M_whole<LDX>(a, q, i, K, X), sm.red);
-      (void)invert_panels<RS, RC, LDX>(N, pow2_scale(mx), X, Xp, W, A, sm);  // ends on a barrier
+      // ends on a barrier; vacancies get 0 on the diagonal of W, and the
+      // Newton step below keeps their rows and columns of V at exactly 0
+      (void)invert_panels<RS, RC, LDX>(N, pow2_scale(mx), X, Xp, W, A, sm,
+                                       q.eps_r ? q.eps_r + (int64_t)(i - 1) * N : nullptr);
       const int eL = half_parity(2 * (i - 1), a.parity), eR = eL ^ 1;
       const int nLi = half_size(N, eL), nRi = half_size(N, eR);
       // One Newton step on the columns R_i of the inverse (Gauss-Jordan

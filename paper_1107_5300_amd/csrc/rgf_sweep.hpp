@@ -183,8 +183,9 @@ __device__ __forceinline__ void sub_mode_sum(cx<T> (&A)[S][C], const double* phi
 // where (B'^T K B')[r][c] = sum of K over the neighbour rows of r and the
 // neighbour columns of c; the column sums go through the wave's LDS scratch.
 // Sums are formed in FP64 and rounded once to T.
-// Returns (wave-uniform) the high word of max_k |E - eps_{h,k}|, for the
-// accuracy guard.
+// Returns (wave-uniform) the high word of max_k |E - eps_{h,k}| over the
+// rows present, for the accuracy guard, with bit 31 set if the half-slice
+// has a vacancy.
 template <typename T, int NW, int S, int C>
 __device__ __forceinline__ uint32_t build_M(cx<T> (&A)[S][C], const SweepArgs& a,
                                             const Tuple& q, int h, const cx<double>* K,
@@ -199,7 +200,7 @@ __device__ __forceinline__ uint32_t build_M(cx<T> (&A)[S][C], const SweepArgs& a
   const double* eps_slice = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
   K = opaque_uniform(K);
   if (eps_slice) eps_slice = opaque_uniform(eps_slice);
-  double dre[S];
+  double dre[S];  // E - eps of the lane's rows: -inf at a vacancy (eps = +inf)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int r = lane + 64 * s;
@@ -249,11 +250,36 @@ __device__ __forceinline__ uint32_t build_M(cx<T> (&A)[S][C], const SweepArgs& a
   }
   if (h == 0) sub_mode_sum<T, NW, S, C>(A, a.phi, q.sig, a.P, n);
   if (h == 2 * a.L - 1) sub_mode_sum<T, NW, S, C>(A, a.phi + (size_t)a.P * NP, q.sig, a.P, n);
+  // vacancies: their rows and columns become the identity's, so the inverse
+  // is that of the lattice without them (the caller zeroes their own
+  // diagonal entries of the inverse)
+  bool vl = false;
+#pragma unroll
+  for (int s = 0; s < S; ++s) vl = vl || isinf(dre[s]);
+  const bool anyv = __builtin_amdgcn_ballot_w64(vl) != 0;
+  if (anyv) {
+    // the wave's vacant columns as a mask (bit j: column w C + j)
+    const int cl = w * C + lane;
+    const uint64_t cm = __builtin_amdgcn_ballot_w64(lane < C && cl < n &&
+                                                    is_vacancy(eps_slice[half_row(cl, e)]));
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int c = w * C + j;
+      const bool vc = ((cm >> j) & 1u) != 0u;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = lane + 64 * s;
+        if (isinf(dre[s]) || vc) A[s][j] = mk<T>((r == c) ? T(1) : T(0), T(0));
+      }
+    }
+  }
   uint32_t dk = 0u;
 #pragma unroll
   for (int s = 0; s < S; ++s)
-    if (lane + 64 * s < n) dk = max(dk, mag_hi(fabs(dre[s])));
-  return wave_max_u32(dk);
+    if (lane + 64 * s < n && !isinf(dre[s])) dk = max(dk, mag_hi(fabs(dre[s])));
+  // bit 31 (never set in the high word of a magnitude) flags a vacancy
+  dk = wave_max_u32(dk);
+  return anyv ? (dk | 0x80000000u) : dk;
 }
 
 // One entry of M_h in FP64 (for the refinement residual), r, c < NP.
@@ -263,11 +289,11 @@ __device__ __forceinline__ cx<double> m_entry(const SweepArgs& a, const Tuple& q
   const int e = half_parity(h, a.parity);
   const int n = half_size(a.N, e);
   if (r >= n || c >= n) return mk((r == c) ? 1.0 : 0.0, 0.0);
+  const double* eps_slice = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
+  if (eps_slice && (is_vacancy(eps_slice[half_row(r, e)]) || is_vacancy(eps_slice[half_row(c, e)])))
+    return mk((r == c) ? 1.0 : 0.0, 0.0);  // vacancy: identity row and column
   cx<double> v = mk(0.0, 0.0);
-  if (r == c) {
-    const double* eps_slice = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
-    v = mk(q.z.re - (eps_slice ? eps_slice[half_row(r, e)] : 0.0), q.z.im);
-  }
+  if (r == c) v = mk(q.z.re - (eps_slice ? eps_slice[half_row(r, e)] : 0.0), q.z.im);
   const double mt2 = -(a.t * a.t);
   if (!(h & 1)) {
     if (h > 0) v = cadd(v, cscale(ldg(K + (size_t)c * NP + r), mt2));
@@ -294,6 +320,23 @@ __device__ __forceinline__ cx<double> m_entry(const SweepArgs& a, const Tuple& q
   return v;
 }
 
+// Zeroes the diagonal entries of g_h (in K, and in K2 if non-null) at the
+// vacant rows of half-slice h: M_h holds the identity's row and column
+// there, so the inverse holds 1 where the removed site's Green's function
+// is 0. Block-wide; the caller orders it between barriers.
+template <int NP>
+__device__ __forceinline__ void zero_vacant_diag(const SweepArgs& a, const Tuple& q, int h,
+                                                 cx<double>* K, cx<double>* K2) {
+  const int e = half_parity(h, a.parity);
+  const int n = half_size(a.N, e);
+  const double* eps_slice = q.eps_r + (int64_t)(h >> 1) * a.N;
+  for (int r = threadIdx.x; r < n; r += blockDim.x)
+    if (is_vacancy(eps_slice[half_row(r, e)])) {
+      stg(K + (size_t)r * NP + r, mk(0.0, 0.0));
+      if (K2) stg(K2 + (size_t)r * NP + r, mk(0.0, 0.0));
+    }
+}
+
 // One half-slice step: reads g_{h-1} from Kprev and G1_{h-1} from G1, writes
 // g_h to Kout and G1_h to G1 (in place). Kprev != Kout when REFINE (the
 // residual regenerates M_h from Kprev after Kout holds the FP32 inverse);
@@ -310,7 +353,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
   const int e = half_parity(h, a.parity);
   const int n = half_size(a.N, e);
   const int n1 = half_size(a.N, half_parity(0, a.parity));
-  uint32_t dkey;  // high word of max_k |E - eps_{h,k}| (wave-uniform)
+  uint32_t dkey;  // high word of max_k |E - eps_{h,k}| | vacancy bit (wave-uniform)
   if constexpr (sizeof(TJ) == sizeof(double)) {
     dkey = build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
     const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));
@@ -320,8 +363,10 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
       const double km = tile_absmax_wave(A);
       if (lane_id() == 0) sm.kred[w] = km;
     }
-    store_unpermuted<double, double, NW, S, C>(A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout,
-                                               h == 0 ? G1out : nullptr);
+    // (a vacancy's diagonal entry is zeroed by the store)
+    store_unpermuted<double, double, NW, S, C>(
+        A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout, h == 0 ? G1out : nullptr,
+        (dkey >> 31) ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr, e);
   } else {
     cx<float> AJ[S][C];
     dkey = build_M<float, NW, S, C>(AJ, a, q, h, Kprev, sm.wbuf + w * NP);
@@ -333,11 +378,15 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
       const double km = tile_absmax_wave(AJ);
       if (lane_id() == 0) sm.kred[w] = km;
     }
-    store_unpermuted<float, double, NW, S, C>(AJ, n, f,
-                                              reinterpret_cast<cx<float>*>(sm.wbuf),
-                                              sm.pivrow, sm.pinv, Kout,
-                                              (h == 0 && !REFINE) ? G1out : nullptr);
+    // without refinement the store zeroes a vacancy's diagonal entry; the
+    // refinement keeps the identity's 1 there until it has converged
+    store_unpermuted<float, double, NW, S, C>(
+        AJ, n, f, reinterpret_cast<cx<float>*>(sm.wbuf), sm.pivrow, sm.pinv, Kout,
+        (h == 0 && !REFINE) ? G1out : nullptr,
+        (!REFINE && (dkey >> 31)) ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr, e);
   }
+  [[maybe_unused]] const bool vac = (dkey >> 31) != 0;  // block-uniform: every wave holds every row
+  dkey &= 0x7FFFFFFFu;
   __syncthreads();
   if (threadIdx.x == 0) {  // the next write of kred follows two more barriers
     double km = sm.kred[0];
@@ -415,6 +464,10 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
                                                  nullptr);
       __syncthreads();
     }
+    if (vac) {
+      zero_vacant_diag<NP>(a, q, h, Kout, nullptr);
+      __syncthreads();
+    }
     if (h == 0) {
       for (int i = threadIdx.x; i < NP * NP; i += NW * 64) stg(G1out + i, ldg(Kout + i));
       __syncthreads();
@@ -459,8 +512,9 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
 // padded with the identity; every entry is formed in FP64 and rounded once
 // to T. K (g of the previous half-slice) is complex symmetric, so entry
 // (r, c) reads K[r][c] with the 16 lanes of a row group on 16 consecutive
-// columns (coalesced). Returns (wave-uniform) the high word of
-// max_k |E - eps_{h,k}|, for the accuracy guard.
+// columns (coalesced). Returns (block-uniform) the high word of
+// max_k |E - eps_{h,k}| over the rows present, for the accuracy guard, with
+// bit 31 set if the half-slice has a vacancy.
 // If Mout is non-null, M_h is also stored there in FP64, row-major
 // (Mout[r NP + c]; M_h is complex symmetric, so it reads column-major too).
 template <typename T>
@@ -485,12 +539,39 @@ __device__ __forceinline__ uint32_t mgj_build(MgjTile<T>& D, const SweepArgs& a,
   K = opaque_uniform(K);
   const int c = 16 * w + li;
   const int c0 = nb_lo(c, e), c1 = nb_hi(c, e);
-  uint32_t dk = 0u;
+  // max |E - eps| over the rows present (rows lane and lane + 64 of every
+  // wave: block-uniform) and the vacancies as a 128-bit row mask in scalar
+  // registers (word i: rows 32 i .. 32 i + 31)
+  uint32_t dk = 0u, vm[4];
+  {
+    const int l0 = lane_id();
+    bool v0 = false, v1 = false;
+    if (l0 < n) {
+      const double ev = eps_slice ? eps_slice[half_row(l0, e)] : 0.0;
+      v0 = is_vacancy(ev);
+      if (!v0) dk = mag_hi(fabs(q.z.re - ev));
+    }
+    if (l0 + 64 < n) {
+      const double ev = eps_slice ? eps_slice[half_row(l0 + 64, e)] : 0.0;
+      v1 = is_vacancy(ev);
+      if (!v1) dk = max(dk, mag_hi(fabs(q.z.re - ev)));
+    }
+    const uint64_t b0 = __builtin_amdgcn_ballot_w64(v0), b1 = __builtin_amdgcn_ballot_w64(v1);
+    vm[0] = (uint32_t)b0;
+    vm[1] = (uint32_t)(b0 >> 32);
+    vm[2] = (uint32_t)b1;
+    vm[3] = (uint32_t)(b1 >> 32);
+  }
+  dk = wave_max_u32(dk);
+  const bool anyv = (vm[0] | vm[1] | vm[2] | vm[3]) != 0u;
+  // column c = 16 w + li lies in word w / 2 (wave-uniform)
+  const uint32_t vmc = (w >> 1) == 0 ? vm[0] : (w >> 1) == 1 ? vm[1] : (w >> 1) == 2 ? vm[2] : vm[3];
+  const bool vc = ((vmc >> (c & 31)) & 1u) != 0u;
 #pragma unroll
   for (int I = 0; I < MG_TI; ++I)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = 16 * I + mgj_row<T>(v, lk);
+      const int r = 16 * I + mgj_row<T>(v, lk);   // in word I / 2
       cx<double> x = mk((r == c) ? 1.0 : 0.0, 0.0);
       if (r < n && c < n) {
         x = mk(0.0, 0.0);
@@ -513,7 +594,6 @@ __device__ __forceinline__ uint32_t mgj_build(MgjTile<T>& D, const SweepArgs& a,
         }
         if (r == c) {
           const double d = q.z.re - (eps_slice ? eps_slice[half_row(r, e)] : 0.0);
-          dk = max(dk, mag_hi(fabs(d)));
           x = cadd(x, mk(d, q.z.im));
         }
         if (ph) {  // lead self-energy on the first and the last half-slice
@@ -524,12 +604,14 @@ __device__ __forceinline__ uint32_t mgj_build(MgjTile<T>& D, const SweepArgs& a,
           }
         }
       }
+      // a vacancy's row and column are the identity's
+      if (anyv && (vc || ((vm[I >> 1] >> (r & 31)) & 1u))) x = mk((r == c) ? 1.0 : 0.0, 0.0);
       mgj_set(D, I, v, mk<T>((T)x.re, (T)x.im));
       if (Mout) stg(Mout + (size_t)r * NP + c, x);
       // bound the loads in flight (register pressure)
       if ((v & 1) == 1) __builtin_amdgcn_sched_barrier(0);
     }
-  return wave_max_u32(dk);
+  return anyv ? (dk | 0x80000000u) : dk;
 }
 
 // g = M_h^{-1} into Kout by the matrix-core Gauss-Jordan in precision T
@@ -579,6 +661,8 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
     dkey = mgj_inverse_to<float>(a, q, h, Kprev, Kout, (h == 0 && !REFINE) ? G1out : nullptr, sm,
                                  *reinterpret_cast<MgjSmem<float>*>(&ms64),
                                  REFINE ? Mbuf : nullptr);
+  const bool vac = (dkey >> 31) != 0;  // block-uniform
+  dkey &= 0x7FFFFFFFu;
   __syncthreads();
   if (threadIdx.x == 0) {  // kred is written again only after further barriers
     double km = sm.kred[0];
@@ -586,6 +670,10 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
     for (int i = 1; i < NW; ++i) km = max(km, sm.kred[i]);
     sm.ksum += km;
     if (dkey < mag_hi(kChiralWindow * fabs(a.t))) sm.ksum_c += km;
+  }
+  if (!REFINE && vac) {
+    zero_vacant_diag<NP>(a, q, h, Kout, h == 0 ? G1out : nullptr);
+    __syncthreads();
   }
   if constexpr (REFINE) {
     // Newton's iteration in FP64 on the matrix cores from the FP32 start:
@@ -634,6 +722,10 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
     }
     if (!converged) {
       (void)mgj_inverse_to<double>(a, q, h, Kprev, Kout, nullptr, sm, ms64);
+      __syncthreads();
+    }
+    if (vac) {
+      zero_vacant_diag<NP>(a, q, h, Kout, nullptr);
       __syncthreads();
     }
     if (h == 0) {

@@ -36,7 +36,7 @@ def test_version_and_strings():
     lib = L.lib()
     a, b = ctypes.c_int(), ctypes.c_int()
     assert lib.rgf_version(ctypes.byref(a), ctypes.byref(b)) == 0
-    assert (a.value, b.value) == (1, 2)
+    assert (a.value, b.value) == (1, 3)
     assert lib.rgf_status_string(-1) == b"RGF_ERR_INVALID_ARG"
     assert lib.rgf_status_string(-3) == b"RGF_ERR_WORKSPACE"
 
