@@ -139,9 +139,16 @@ def gpu_run(Es, eps, precision, steps, warmup, tune=True):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = [a.elapsed_time(b) for a, b in evs]
+    if precision == "mixed":
+        P.refine_stats(reset=True)
     T, st = P.conductance(rib, E, ep, precision=precision, workspace=ws, return_status=True)
     torch.cuda.synchronize()
-    return wall, ev_ms, T.cpu().numpy()[0], st.cpu().numpy()[0], tile
+    refine = None
+    if precision == "mixed":   # counters of the checking call (one full sweep of the workload)
+        c = P.refine_stats()
+        refine = dict(c, newton_updates_per_half_slice=c["newton_updates"] / max(c["refined"], 1),
+                      fp64_reinversion_frac=c["fp64_reinversions"] / max(c["refined"], 1))
+    return wall, ev_ms, T.cpu().numpy()[0], st.cpu().numpy()[0], tile, refine
 
 
 def lead_time_ms(Es, reps=5):
@@ -168,17 +175,27 @@ def lead_time_ms(Es, reps=5):
 
 
 def csrc_fingerprint():
-    """sha256 prefix over the HIP sources (the same rule the traffic summary
-    under profiles/ records), so a traffic figure is only reported for the
-    kernel it was measured on."""
+    """sha256 prefix over the translation unit of the forward sweep kernels
+    (csrc/rgf_forward.hip and every header it includes, transitively), the
+    rule the counter summaries under profiles/ record, so a counter figure
+    is only reported for the kernel code it was measured on."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_1107_5300_amd", "csrc")
+    todo, seen = [os.path.join(d, "rgf_forward.hip")], set()
+    while todo:
+        f = os.path.normpath(todo.pop())
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.add(f)
+        with open(f) as fh:
+            for inc in re.findall(r'^#include "([^"]+)"', fh.read(), re.M):
+                todo.append(os.path.join(os.path.dirname(f), inc))
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in sorted(seen, key=lambda x: os.path.relpath(x, ROOT)):
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -361,6 +378,70 @@ def row_adjoint(args):
                       "max_abs_dT_vs_oracle": out[p]["terr"],
                       "max_rel_grad_err_vs_oracle": out[p]["derr"], "tile": out[p]["tile"]}
                   for p in out},
+    }
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
+          flush=True)
+
+
+def row_segments(args):
+    """Small batch of the metric's ribbon: N = 240, L = 2000 (workload
+    disorder_n240), 8 of its 256 energies, where the sequential sweep keeps
+    8 of the 256 compute units busy. rgf_conductance_segments splits each
+    tuple along the length (automatic segment count) and joins the segments;
+    timed beside rgf_conductance on the same tuples."""
+    import torch
+
+    import paper_1107_5300_amd as P
+    Es = W.energies(WORKLOAD)[::32]
+    eps = W.disorder(L, N, WDIS, r=0)
+    sample = [1, 5]
+    want = None
+    if not args.no_cpu:
+        want, wall_c, nw = _pool_map(_oracle_T_job, [(N, L, Es[j], eps) for j in sample])
+        _say("segments: oracle sample done")
+    dev = torch.device("cuda:0")
+    rib = P.Ribbon(N, L, 0, W.T_HOP, W.ETA)
+    E = torch.tensor(Es, device=dev)
+    ep = torch.tensor(eps[None], device=dev)
+    ws1, ws2 = P.Workspace(), P.Workspace()
+    G = P.conductance_segments(rib, E, ep, workspace=ws1, return_segments=True)[1]
+    wall_s, ev_s = _events(torch, lambda: P.conductance_segments(rib, E, ep, workspace=ws1),
+                           args.steps, args.warmup)
+    wall_q, ev_q = _events(torch, lambda: P.conductance(rib, E, ep, workspace=ws2),
+                           args.steps, args.warmup)
+    Ts, sts = P.conductance_segments(rib, E, ep, workspace=ws1, return_status=True)
+    Tq = P.conductance(rib, E, ep, workspace=ws2)
+    torch.cuda.synchronize()
+    Ts, sts, Tq = Ts.cpu().numpy()[0], sts.cpu().numpy()[0], Tq.cpu().numpy()[0]
+    dT = None if want is None else max(abs(Ts[j] - w) for j, w in zip(sample, want))
+    steps = len(Es) * L
+    fl = flops_per_slice_step(N)
+    ev_mean = float(np.mean(ev_s)) / 1e3
+    line = {
+        "metric": "RGF slice-steps/s at N=240, L=2000, 8 energies (parallel in length)",
+        "value": steps * args.steps / wall_s, "unit": "slice-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "disorder_n240 at 8 of its 256 energies", "N": N, "L": L,
+                   "n_energies": len(Es), "n_real": 1, "segments": G,
+                   "slice_steps_per_step": steps},
+        "roofline": {"bound": "alu", "achieved": fl * steps / ev_mean / 1e12,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fl * steps / ev_mean / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "rgf_seg_sweep_kernel + rgf_seg_join_kernel",
+                     "flops_note": "useful flops of one sequential sweep (4N^3 per "
+                                   "slice-step); the segments do about 1.7x that",
+                     "event_ms_mean": ev_mean * 1e3},
+        "cpu_baseline": None,
+        "accuracy": {"sampled_energies": sample, "max_abs_dT_vs_oracle": dT,
+                     "max_abs_dT_vs_sequential_all": float(np.abs(Ts - Tq).max()),
+                     "tuples_not_ok": int((sts != 0).sum()), "bar": ACC_TOL},
+        "rates": {"segments": {"slice_steps_per_s": steps * args.steps / wall_s,
+                               "event_ms_mean": ev_mean * 1e3},
+                  "sequential": {"slice_steps_per_s": steps * args.steps / wall_q,
+                                 "event_ms_mean": float(np.mean(ev_q))},
+                  "speedup": wall_q / wall_s},
     }
     print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)),
           flush=True)
@@ -713,12 +794,14 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--row", default="main",
-                    choices=["main", "adjoint", "batched", "ldos", "wide", "wide-grad"],
+                    choices=["main", "adjoint", "batched", "ldos", "wide", "wide-grad",
+                             "segments"],
                     help="main: the N=240 sweep (the metric); adjoint: gradient sweep of the "
                          "N=120 workload; batched: the mixed-width batched launch; ldos: "
                          "local density of states of the N=120 workload; wide: the N=480 "
                          "workload through the blocked half-slice inversion; wide-grad: its "
-                         "checkpointed gradient")
+                         "checkpointed gradient; segments: 8 energies of the N=240 ribbon, "
+                         "parallel in length")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark measures one GPU; --gpus {args.gpus} is not supported "
@@ -735,6 +818,8 @@ def main():
         return row_wide(args)
     if args.row == "wide-grad":
         return row_wide_grad(args)
+    if args.row == "segments":
+        return row_segments(args)
 
     Es = W.energies(WORKLOAD)
     eps = W.disorder(L, N, WDIS, r=0)
@@ -748,10 +833,11 @@ def main():
     modes = ["fp64", "mixed"] if args.precision == "auto" else [args.precision]
     results = {}
     for prec in modes:
-        wall, ev_ms, T, st, tile = gpu_run(Es, eps, prec, args.steps, args.warmup,
-                                           tune=not args.no_tune)
+        wall, ev_ms, T, st, tile, refine = gpu_run(Es, eps, prec, args.steps, args.warmup,
+                                                   tune=not args.no_tune)
         dT = max((abs(T[j] - v) for j, v in oracle_T.items()), default=None)
-        results[prec] = dict(wall=wall, ev_ms=ev_ms, T=T, st=st, dT=dT, tile=tile)
+        results[prec] = dict(wall=wall, ev_ms=ev_ms, T=T, st=st, dT=dT, tile=tile,
+                             refine=refine)
         _say(f"{prec}: {wall / args.steps * 1e3:.1f} ms per step")
     lead_ms = lead_time_ms(Es)
     if args.calibrate_copy:
@@ -847,7 +933,8 @@ def main():
                                                else float(results[p]["dT"])),
                       "max_abs_dT_vs_fp64_all_energies": results[p].get("dT_vs_fp64_all"),
                       "tile": results[p]["tile"],
-                      "matrix_core_inversion": bool(getattr(results[p]["tile"], "mgj", False))}
+                      "matrix_core_inversion": bool(getattr(results[p]["tile"], "mgj", False)),
+                      "refinement": results[p]["refine"]}
                 for p in results},
     }
     print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)), flush=True)

@@ -190,12 +190,53 @@ int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev,
              int32_t* status_out, void* workspace, size_t workspace_bytes,
              void* hip_stream);
 
+/* Conductance with the recursion split along the ribbon length (parallel in
+ * L), for batches of (realization, energy) tuples too small to fill the
+ * GPU. The paper remarks that parallelising the calculation needs a
+ * modification of the recursion of Eqs. (4)-(5); here each tuple's L slices
+ * are cut into G segments of consecutive slices, each closed at both ends by
+ * the self-energy of a semi-infinite pristine ribbon (the leads' own at the
+ * ribbon's ends). Every segment is solved on its own by the left-connected
+ * sweep (corners G[a, b], G[b, b]) and, for all but the first, the same
+ * sweep over the reversed segment (corner G[a, a]), each on a workgroup of
+ * its own; the segments are then joined left to right by Dyson's equation
+ * (Eq. (3)) across the inter-slice bonds, which also takes the closing
+ * self-energies out again.
+ * The result is T of Eq. (2) as from rgf_conductance (equal up to rounding);
+ * the work is about 1.7x that of one sweep, spread over up to (2G - 1)
+ * workgroups per tuple.
+ *   n_segments   G; 0 picks G so that the tuples' items about fill the GPU
+ *                (G = 1 when the tuples alone do); clamped to [1, min(L, 1024)]
+ *   segments_out (may be NULL) receives the G used
+ * Other arguments as for rgf_conductance, FP64 only, widths up to
+ * RGF_TILE_MAX_WIDTH (RGF_ERR_UNSUPPORTED above). Tuples the accuracy guard
+ * rejects are recomputed by the whole-slice sweep, as in rgf_conductance.
+ * The workspace is rgf_segments_workspace_bytes(desc, n_energies, n_real,
+ * n_segments) bytes: per tuple and segment three ceil(N/2)^2 complex128
+ * matrices (padded to the tile), six more per joining workgroup, the lead
+ * tables and a reversed copy of the on-site energies. */
+size_t rgf_segments_workspace_bytes(const rgf_ribbon_desc* desc, int64_t n_energies,
+                                    int64_t n_real, int32_t n_segments);
+int rgf_conductance_segments(const rgf_ribbon_desc* desc, const double* energies_ev,
+                             int64_t n_energies, const double* onsite_eps_ev, int64_t n_real,
+                             int32_t n_segments, double* T_out, int32_t* status_out,
+                             int32_t* segments_out, void* workspace, size_t workspace_bytes,
+                             void* hip_stream);
+
 /* Several ribbons of different widths in one call (energy sweeps x disorder
  * realizations x widths). Ribbon d uses descs[d], its on-site energies at
  * onsite_eps_ev + eps_offsets[d] ([n_real][L_d][N_d]) and writes
  * T_out + T_offsets[d] ([n_real][n_energies]) and the same offset into
  * status_out (may be NULL). All ribbons share energies_ev, n_real and
- * precision. Work is ordered largest width first. */
+ * precision. The ribbons run concurrently: each gets its own part of the
+ * workspace and a share of the persistent workgroups proportional to its
+ * work (n^3 L per tuple, n = ceil(N/2)), and all but the costliest run on
+ * library-owned streams (default priority, created once per device) that
+ * are forked from hip_stream by an event and joined back to it before the
+ * call's work ends, so the call stays stream-ordered and capturable (the
+ * streams are created by the first call with several ribbons on a device,
+ * which must not be made under stream capture). The workspace is the sum of
+ * the ribbons' parts. With one ribbon this is rgf_conductance. */
 size_t rgf_batched_workspace_bytes(const rgf_ribbon_desc* descs, int32_t n_desc,
                                    int64_t n_energies, int64_t n_real,
                                    int precision);
@@ -276,6 +317,22 @@ int rgf_lead_modes(const rgf_ribbon_desc* desc, const double* energies_ev,
 size_t rgf_autotune_workspace_bytes(const rgf_ribbon_desc* desc, int precision);
 int rgf_autotune(const rgf_ribbon_desc* desc, int precision, void* workspace,
                  size_t workspace_bytes, void* hip_stream, int32_t* chosen_out);
+
+/* Diagnostics of the mixed mode (RGF_PREC_MIXED; the accuracy discussion
+ * of the paper names single precision as the error source, and the mixed
+ * mode inverts each half-slice in FP32, refines the inverse with FP64 Newton
+ * steps and re-inverts it in FP64 when they do not converge). Every forward
+ * sweep of the conductance entry points in that mode adds to three counters
+ * of the current device, kept by the library (no workspace):
+ *   counts_out[0]  half-slices inverted in FP32 and refined,
+ *   counts_out[1]  Newton updates applied,
+ *   counts_out[2]  half-slices re-inverted in FP64.
+ * Waits for hip_stream (not for other streams), then copies the counters to
+ * the host array counts_out[3]; reset != 0 zeroes them afterwards. Sweeps
+ * running concurrently on the device add to the same counters. Not for use
+ * inside stream capture. Returns RGF_ERR_INVALID_ARG for a NULL counts_out,
+ * RGF_ERR_HIP without a usable device. */
+int rgf_refine_stats(uint64_t* counts_out, int reset, void* hip_stream);
 
 /* Static descriptions. rgf_last_error_message is thread-local and describes
  * the last non-OK return of this thread. */

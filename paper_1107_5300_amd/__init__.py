@@ -12,6 +12,7 @@ from .rgf import (  # noqa: F401
     conductance,
     conductance_batched,
     conductance_noalloc,
+    conductance_segments,
     grad,
     ldos,
     RGFConductance,
@@ -21,4 +22,5 @@ from .rgf import (  # noqa: F401
     workspace_bytes,
     version,
     autotune,
+    refine_stats,
 )

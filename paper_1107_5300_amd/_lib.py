@@ -40,9 +40,12 @@ EXPORTED = (
     "rgf_batched_workspace_bytes",
     "rgf_conductance_batched",
     "rgf_conductance_noalloc",
+    "rgf_segments_workspace_bytes",
+    "rgf_conductance_segments",
     "rgf_lead_self_energy",
     "rgf_autotune_workspace_bytes",
     "rgf_autotune",
+    "rgf_refine_stats",
     "rgf_status_string",
     "rgf_last_error_message",
     "rgf_version",
@@ -100,6 +103,11 @@ def _declare(lib):
                                             _vp, _vp, _vp, _sz, _vp]
     lib.rgf_conductance_noalloc.restype = _int
     lib.rgf_conductance_noalloc.argtypes = [_pdesc, _vp, _i64, _vp, _i64, _int, _vp, _vp, _vp]
+    lib.rgf_segments_workspace_bytes.restype = _sz
+    lib.rgf_segments_workspace_bytes.argtypes = [_pdesc, _i64, _i64, _i32]
+    lib.rgf_conductance_segments.restype = _int
+    lib.rgf_conductance_segments.argtypes = [_pdesc, _vp, _i64, _vp, _i64, _i32, _vp, _vp,
+                                             ctypes.POINTER(_i32), _vp, _sz, _vp]
     lib.rgf_lead_self_energy.restype = _int
     lib.rgf_lead_self_energy.argtypes = [_pdesc, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                          _vp]
@@ -107,6 +115,8 @@ def _declare(lib):
     lib.rgf_autotune_workspace_bytes.argtypes = [_pdesc, _int]
     lib.rgf_autotune.restype = _int
     lib.rgf_autotune.argtypes = [_pdesc, _int, _vp, _sz, _vp, ctypes.POINTER(_i32)]
+    lib.rgf_refine_stats.restype = _int
+    lib.rgf_refine_stats.argtypes = [ctypes.POINTER(ctypes.c_uint64), _int, _vp]
     lib.rgf_status_string.restype = ctypes.c_char_p
     lib.rgf_status_string.argtypes = [_int]
     lib.rgf_last_error_message.restype = ctypes.c_char_p

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librgf.so")
 
 SOURCES = ["rgf_api.cpp", "rgf_lead.hip", "rgf_forward.hip", "rgf_adjoint.hip", "rgf_ldos.hip",
-           "rgf_large.hip", "rgf_noalloc.hip"]
+           "rgf_large.hip", "rgf_noalloc.hip", "rgf_segment.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -112,6 +112,13 @@ int main() {
   rgf_ribbon_desc t = desc(480, 20);
   CHECK(rgf_autotune_workspace_bytes(&t, 0) > 0);
   CHECK(rgf_autotune_workspace_bytes(&t, 1) == 0);
+  CHECK(rgf_refine_stats(nullptr, 0, nullptr) == RGF_ERR_INVALID_ARG);
+  // segments along the length: argument errors before anything is enqueued
+  rgf_ribbon_desc sg = desc(60, 40);
+  CHECK(rgf_segments_workspace_bytes(&sg, 4, 1, -1) == 0);
+  CHECK(rgf_segments_workspace_bytes(&t, 4, 1, 0) == 0);   /* N = 480: unsupported */
+  CHECK(rgf_conductance_segments(&sg, nullptr, 4, nullptr, 1, 4, nullptr, nullptr, nullptr,
+                                 nullptr, 0, nullptr) != RGF_OK);
   int a = 0, b = 0;
   CHECK(rgf_version(&a, &b) == RGF_OK && a == RGF_ABI_VERSION_MAJOR);
   CHECK(strcmp(rgf_status_string(RGF_ERR_WORKSPACE), "RGF_ERR_WORKSPACE") == 0);

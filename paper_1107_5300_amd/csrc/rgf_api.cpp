@@ -241,6 +241,30 @@ int kernel_occupancy(const void* k, int threads) {
 }
 }  // namespace
 
+// Counters of the mixed mode's refinement, one copy per device: refined
+// half-slices, Newton updates, FP64 re-inversions (rgf_refine_stats).
+__device__ unsigned long long g_refine_stats[3];
+
+namespace {
+std::map<int, unsigned long long*> g_refine_ptr;  // device -> address of g_refine_stats
+}  // namespace
+
+unsigned long long* device_refine_stats() {
+  int dev = 0;
+  if (!current_device(&dev)) return nullptr;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_refine_ptr.find(dev);
+  if (it != g_refine_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_refine_stats)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;  // not cached: a later call may succeed
+  }
+  auto* c = static_cast<unsigned long long*>(ptr);
+  g_refine_ptr[dev] = c;
+  return c;
+}
+
 int device_cu_count() {
   int dev = 0;
   if (!current_device(&dev)) return 256;
@@ -290,6 +314,65 @@ static int hip_fail(hipError_t e) {
   return fail(RGF_ERR_HIP, "HIP error %d: %s", (int)e, hipGetErrorString(e));
 }
 
+// ------------------------------------------------------- segments (in L)
+
+int make_seg_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int n_segments,
+                  SegPlan* sp) {
+  if (n_segments < 0) return fail(RGF_ERR_INVALID_ARG, "n_segments = %d < 0", n_segments);
+  SegPlan q;
+  memset(&q, 0, sizeof(q));
+  // the ribbon's own plan: lead tables, and flags and slots for the
+  // whole-slice recomputation of rejected tuples (one slot per tuple at most)
+  int st = make_plan(d, nE, nreal, RGF_PREC_FP64, 0, 0, &q.fwd);
+  if (st != RGF_OK) return st;
+  if (q.fwd.large)
+    return fail(RGF_ERR_UNSUPPORTED,
+                "width_n = %d: the segment sweep holds half-slices of up to %d rows",
+                d->width_n, kTileMaxRows);
+  if (!seg_supported(q.fwd.tile))
+    return fail(RGF_ERR_UNSUPPORTED, "no segment kernel for width_n = %d", d->width_n);
+  // the mode tables of both row classes: the leads of a ribbon of the same
+  // width, odd length and parity 0 (left lead on class 0, right lead on
+  // class 1); sigma is the same for every lead of this width
+  rgf_ribbon_desc da = *d;
+  da.parity = 0;
+  da.length_l = d->length_l | 1;
+  st = make_plan(&da, nE, nreal, RGF_PREC_FP64, 0, 0, &q.aux);
+  if (st != RGF_OK) return st;
+  if (q.aux.phi_ld != q.fwd.phi_ld)  // both plans pick the tile by the width alone
+    return fail(RGF_ERR_UNSUPPORTED, "width_n = %d: lead tables of different layouts",
+                d->width_n);
+  const int NP = q.fwd.tile.NP();
+  const int64_t nt = q.fwd.ntuples;
+  const int ncu = device_cu_count();
+  const int occ = kernel_occupancy(seg_sweep_kernel(q.fwd.tile), q.fwd.tile.threads());
+  const int64_t cap = (int64_t)ncu * occ;
+  int64_t G = n_segments;
+  if (G == 0) G = nt > 0 ? (cap / std::max<int64_t>(nt, 1) + 2) / 2 : 1;  // items ~ the slots
+  G = std::max<int64_t>(1, std::min<int64_t>({G, (int64_t)d->length_l, 1024}));
+  q.G = (int)G;
+  const int64_t nitems = nt * (2 * G - 1);
+  q.sweep_grid = (int)std::max<int64_t>(1, std::min(cap, nitems));
+  q.join_grid = (int)std::max<int64_t>(1, std::min(cap, nt));
+  // lead tables of the reversed ribbon: the part of its plan before the flags
+  size_t off = align_up(q.fwd.total, 256);
+  q.off_aux = off;
+  off = align_up(off + q.aux.off_flags, 256);
+  q.off_eps_rev = off;
+  off = align_up(off + (size_t)nreal * d->length_l * d->width_n * 8, 256);
+  q.off_mats = off;
+  off = align_up(off + (size_t)nt * G * 3 * NP * NP * 16, 256);
+  q.off_scratch = off;
+  off = align_up(off + (size_t)q.join_grid * 6 * NP * NP * 16, 256);
+  q.off_kap = off;
+  off = align_up(off + (size_t)nt * 2 * G * 2 * 8, 256);
+  q.off_flag = off;
+  off = align_up(off + (size_t)nt * 2 * G * 4, 256);
+  q.total = off;
+  *sp = q;
+  return RGF_OK;
+}
+
 }  // namespace rgf
 
 using namespace rgf;
@@ -318,6 +401,36 @@ int rgf_conductance(const rgf_ribbon_desc* desc, const double* energies_ev,
   if (st != RGF_OK) return st;
   hipError_t e = launch_forward(p, energies_ev, onsite_eps_ev, T_out, status_out,
                                 (char*)workspace, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return RGF_OK;
+}
+
+size_t rgf_segments_workspace_bytes(const rgf_ribbon_desc* desc, int64_t n_energies,
+                                    int64_t n_real, int32_t n_segments) {
+  SegPlan sp;
+  if (make_seg_plan(desc, n_energies, n_real, n_segments, &sp) != RGF_OK) return 0;
+  return std::max<size_t>(sp.total, 256);
+}
+
+int rgf_conductance_segments(const rgf_ribbon_desc* desc, const double* energies_ev,
+                             int64_t n_energies, const double* onsite_eps_ev, int64_t n_real,
+                             int32_t n_segments, double* T_out, int32_t* status_out,
+                             int32_t* segments_out, void* workspace, size_t workspace_bytes,
+                             void* hip_stream) {
+  SegPlan sp;
+  int st = make_seg_plan(desc, n_energies, n_real, n_segments, &sp);
+  if (st != RGF_OK) return st;
+  if (segments_out) *segments_out = sp.G;
+  if (n_energies == 0) return RGF_OK;
+  if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
+  if (!T_out) return fail(RGF_ERR_INVALID_ARG, "T_out is NULL");
+  if (workspace_bytes < sp.total)
+    return fail(RGF_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes,
+                sp.total);
+  if (!workspace || ((uintptr_t)workspace) % 256 != 0)
+    return fail(RGF_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  hipError_t e = launch_segments(sp, energies_ev, onsite_eps_ev, T_out, status_out,
+                                 (char*)workspace, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e);
   return RGF_OK;
 }
@@ -411,32 +524,78 @@ int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev, int64_t n_e
 // on the caller's stream, most expensive (N^3 L) first; the workspace is
 // reused from one launch to the next (stream order), so it is sized by the
 // largest plan. The whole sequence can be captured into a hipGraph.
+// Plans of a batched call: every ribbon's plan with a share of the
+// persistent workgroups proportional to its work, and its workspace part at
+// base[d] (the parts are disjoint, so the ribbons can run concurrently).
 static int batched_plans(const rgf_ribbon_desc* descs, int32_t n_desc, int64_t n_energies,
-                         int64_t n_real, int precision, Plan* plans, size_t* bytes) {
+                         int64_t n_real, int precision, Plan* plans, size_t* base,
+                         size_t* bytes) {
   if (!descs) return fail(RGF_ERR_INVALID_ARG, "descs is NULL");
   if (n_desc < 1 || n_desc > 64)
     return fail(RGF_ERR_INVALID_ARG, "n_desc = %d outside [1, 64]", n_desc);
-  size_t mx = 0;
+  double cost[64], total = 0.0;
   for (int d = 0; d < n_desc; ++d) {
     int st = make_plan(&descs[d], n_energies, n_real, precision, 0, 0, &plans[d]);
     if (st != RGF_OK) {
       std::string m = rgf_last_error_message();
       return fail(st, "descs[%d]: %s", d, m.c_str());
     }
-    mx = std::max(mx, plans[d].total);
+    const double n = plans[d].nmax;
+    cost[d] = n * n * n * plans[d].L * (double)std::max<int64_t>(plans[d].ntuples, 1);
+    total += cost[d];
   }
-  *bytes = std::max<size_t>(mx, 256);
+  size_t off = 0;
+  for (int d = 0; d < n_desc; ++d) {
+    if (n_desc > 1) {
+      const int cap = std::max(1, (int)ceil(plans[d].grid * cost[d] / total));
+      int st = make_plan(&descs[d], n_energies, n_real, precision, 0, 0, &plans[d], cap);
+      if (st != RGF_OK) return st;
+    }
+    base[d] = off;
+    off = align_up(off + plans[d].total, 256);
+  }
+  *bytes = std::max<size_t>(off, 256);
   return RGF_OK;
 }
 
 size_t rgf_batched_workspace_bytes(const rgf_ribbon_desc* descs, int32_t n_desc,
                                    int64_t n_energies, int64_t n_real, int precision) {
   Plan plans[64];
-  size_t bytes = 0;
-  if (batched_plans(descs, n_desc, n_energies, n_real, precision, plans, &bytes) != RGF_OK)
+  size_t base[64], bytes = 0;
+  if (batched_plans(descs, n_desc, n_energies, n_real, precision, plans, base, &bytes) !=
+      RGF_OK)
     return 0;
   return bytes;
 }
+
+namespace {
+// Streams the batched call forks onto (default priority, non-blocking), with
+// the events of the fork and the joins; one set per device, used under a
+// lock for the whole enqueue so that concurrent calls do not interleave
+// their records and waits.
+constexpr int kBatchStreams = 7;
+struct BatchPool {
+  bool ok = false;
+  hipStream_t st[kBatchStreams];
+  hipEvent_t fork, join[kBatchStreams];
+};
+std::mutex g_pool_mu;
+std::map<int, BatchPool> g_pool;
+
+BatchPool* batch_pool() {
+  int dev = 0;
+  if (!current_device(&dev)) return nullptr;
+  BatchPool& p = g_pool[dev];
+  if (p.ok) return &p;
+  for (int i = 0; i < kBatchStreams; ++i)
+    if (hipStreamCreateWithFlags(&p.st[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p.join[i], hipEventDisableTiming) != hipSuccess)
+      return nullptr;
+  if (hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+  p.ok = true;
+  return &p;
+}
+}  // namespace
 
 int rgf_conductance_batched(const rgf_ribbon_desc* descs, int32_t n_desc,
                             const int64_t* eps_offsets, const int64_t* T_offsets,
@@ -445,8 +604,8 @@ int rgf_conductance_batched(const rgf_ribbon_desc* descs, int32_t n_desc,
                             double* T_out, int32_t* status_out, void* workspace,
                             size_t workspace_bytes, void* hip_stream) {
   Plan plans[64];
-  size_t bytes = 0;
-  int st = batched_plans(descs, n_desc, n_energies, n_real, precision, plans, &bytes);
+  size_t base[64], bytes = 0;
+  int st = batched_plans(descs, n_desc, n_energies, n_real, precision, plans, base, &bytes);
   if (st != RGF_OK) return st;
   if (n_energies == 0) return RGF_OK;
   if (!energies_ev) return fail(RGF_ERR_INVALID_ARG, "energies_ev is NULL");
@@ -464,19 +623,43 @@ int rgf_conductance_batched(const rgf_ribbon_desc* descs, int32_t n_desc,
   int order[64];
   for (int d = 0; d < n_desc; ++d) order[d] = d;
   std::stable_sort(order, order + n_desc, [&](int x, int y) {
-    const double cx = (double)plans[x].N * plans[x].N * plans[x].N * plans[x].L;
-    const double cy = (double)plans[y].N * plans[y].N * plans[y].N * plans[y].L;
+    const double cx = (double)plans[x].nmax * plans[x].nmax * plans[x].nmax * plans[x].L;
+    const double cy = (double)plans[y].nmax * plans[y].nmax * plans[y].nmax * plans[y].L;
     return cx > cy;
   });
-  for (int i = 0; i < n_desc; ++i) {
-    const int d = order[i];
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto launch = [&](int d, hipStream_t on) {
     const double* eps = onsite_eps_ev ? onsite_eps_ev + eps_offsets[d] : nullptr;
-    hipError_t e = launch_forward(plans[d], energies_ev, eps, T_out + T_offsets[d],
-                                  status_out ? status_out + T_offsets[d] : nullptr,
-                                  (char*)workspace, (hipStream_t)hip_stream);
-    if (e != hipSuccess) return hip_fail(e);
+    return launch_forward(plans[d], energies_ev, eps, T_out + T_offsets[d],
+                          status_out ? status_out + T_offsets[d] : nullptr,
+                          (char*)workspace + base[d], on);
+  };
+  if (n_desc == 1) {
+    hipError_t e = launch(order[0], s);
+    return e == hipSuccess ? RGF_OK : hip_fail(e);
   }
-  return RGF_OK;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  BatchPool* pool = batch_pool();
+  if (!pool) {
+    (void)hipGetLastError();
+    return fail(RGF_ERR_HIP, "could not create the batched call's streams");
+  }
+  // fork: the other ribbons' streams wait for the work queued on s so far
+  hipError_t e = hipEventRecord(pool->fork, s);
+  const int used = std::min(n_desc - 1, kBatchStreams);
+  for (int j = 0; e == hipSuccess && j < used; ++j)
+    e = hipStreamWaitEvent(pool->st[j], pool->fork, 0);
+  // the costliest ribbon on s, the others round-robin on the pool's streams
+  for (int i = 0; e == hipSuccess && i < n_desc; ++i)
+    e = launch(order[i], i == 0 ? s : pool->st[(i - 1) % kBatchStreams]);
+  // join: s waits for every forked stream (also after a failed launch, so
+  // that no stream is left forked from a capture)
+  for (int j = 0; j < used; ++j) {
+    hipError_t r = hipEventRecord(pool->join[j], pool->st[j]);
+    if (r == hipSuccess) r = hipStreamWaitEvent(s, pool->join[j], 0);
+    if (e == hipSuccess) e = r;
+  }
+  return e == hipSuccess ? RGF_OK : hip_fail(e);
 }
 
 // ---------------------------------------------------------------- autotuner
@@ -656,6 +839,19 @@ const char* rgf_status_string(int status) {
 }
 
 const char* rgf_last_error_message(void) { return g_last_error.c_str(); }
+
+int rgf_refine_stats(uint64_t* counts_out, int reset, void* hip_stream) {
+  if (!counts_out) return fail(RGF_ERR_INVALID_ARG, "counts_out is NULL");
+  unsigned long long* c = device_refine_stats();
+  if (!c) return fail(RGF_ERR_HIP, "no device counters (no current HIP device)");
+  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e == hipSuccess) e = hipMemcpy(counts_out, c, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset) {
+    static const uint64_t zeros[3] = {0, 0, 0};
+    e = hipMemcpy(c, zeros, sizeof(zeros), hipMemcpyHostToDevice);
+  }
+  return e == hipSuccess ? RGF_OK : hip_fail(e);
+}
 
 int rgf_version(int* major, int* minor) {
   if (major) *major = RGF_ABI_VERSION_MAJOR;

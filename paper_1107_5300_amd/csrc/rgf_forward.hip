@@ -33,6 +33,7 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_f
   cx<double>* kb[2] = {slot, REFINE ? slot + (size_t)3 * NP * NP : slot};
   cx<double>* gbuf = slot + (size_t)NP * NP;
   cx<double>* rbuf = slot + (size_t)2 * NP * NP;
+  if (threadIdx.x == 0) sm.rf[0] = sm.rf[1] = sm.rf[2] = 0u;
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
@@ -71,6 +72,7 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : (REFINE ? 2 : 3)) void rgf_f
     }
     __syncthreads();
   }
+  if constexpr (REFINE) flush_refine_stats(a, sm);
 }
 
 // The sweep with the matrix-core Gauss-Jordan (rgf_mgj.hpp) for half-slices
@@ -86,6 +88,7 @@ __global__ __launch_bounds__(512, 1) void rgf_fwd_mgj_kernel(SweepArgs a) {
   cx<double>* gbuf = slot + (size_t)NP * NP;
   cx<double>* rbuf = slot + (size_t)2 * NP * NP;
   cx<double>* mbuf = REFINE ? slot + (size_t)4 * NP * NP : nullptr;  // M_h in FP64
+  if (threadIdx.x == 0) sm.rf[0] = sm.rf[1] = sm.rf[2] = 0u;
 
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
@@ -113,6 +116,7 @@ __global__ __launch_bounds__(512, 1) void rgf_fwd_mgj_kernel(SweepArgs a) {
     }
     __syncthreads();
   }
+  if constexpr (REFINE) flush_refine_stats(a, sm);
 }
 
 using FwdKernel = void (*)(SweepArgs);
@@ -212,6 +216,7 @@ hipError_t launch_forward(const Plan& p, const double* E, const double* eps, dou
   a.tchan = tchan;
   a.phi_ld = p.phi_ld;
   a.fb_flags = p.fb_grid > 0 ? reinterpret_cast<int32_t*>(ws + p.off_flags) : nullptr;
+  a.refine_stats = p.precision == RGF_PREC_MIXED ? device_refine_stats() : nullptr;
   const FwdEntry& f = kFwd[p.tile.id];
   if (tchan && p.precision != RGF_PREC_FP64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(tchan ? f.chan : f.k[p.precision], dim3(p.grid), dim3(f.NW * 64), 0, s, a);

@@ -61,6 +61,10 @@ struct SweepArgs {
   // that the whole-slice sweep recomputes, or null
   int32_t* fb_flags;        // [nreal][nE]
   int phi_ld;               // leading dimension of the lead mode tables
+  // mixed mode: device counters of the refinement (refined half-slices,
+  // Newton updates, FP64 re-inversions) that the forward kernels add to, or
+  // null
+  unsigned long long* refine_stats;
 };
 
 // Accuracy guard of the half-slice recursion. Each half-slice inversion
@@ -101,7 +105,21 @@ struct SweepSmem {
   double ksum;       // running sum of kappa_h over the forward sweep
   double ksum_c;     // the same over the sublattice-symmetric half-slices
   int flag;
+  // refinement counts of this workgroup (thread 0): refined half-slices,
+  // Newton updates, FP64 re-inversions; the forward kernels zero them at
+  // their start and add them to SweepArgs::refine_stats at their end
+  unsigned rf[3];
 };
+
+// Adds the workgroup's refinement counts to the device counters (thread 0).
+template <typename Smem>
+__device__ __forceinline__ void flush_refine_stats(const SweepArgs& a, const Smem& sm) {
+  if (threadIdx.x == 0 && a.refine_stats) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (sm.rf[i]) atomicAdd(a.refine_stats + i, (unsigned long long)sm.rf[i]);
+  }
+}
 
 // Largest |re| + |im| of a register tile across the wave (from the high 32
 // bits of the magnitudes, so it is a lower bound within 2^-20).
@@ -126,12 +144,21 @@ __device__ __forceinline__ bool t_in_range(double T, int P) {
   return T >= -1e-6 && T <= (double)P + 1e-6;
 }
 
-// Per-tuple constants.
+// Per-tuple constants. hs, he: the first and the last half-slice of the
+// sweep (0 and 2L - 1 for the whole chain; a segment's ends when the chain
+// is solved in segments, whose coupling to the left is then left out). The
+// mode-space self-energy Phi diag(sigma) Phi^T is added at both: from phi_s
+// and phi_e, or, where these are null, from the lead tables (left lead at
+// hs, right lead at he). g1: whether the sweep forms the running product G1.
 struct Tuple {
   int64_t r, e, idx;
   cx<double> z;
   const cx<double>* sig;
   const double* eps_r;
+  const double* phi_s;
+  const double* phi_e;
+  int hs, he;
+  bool g1;
 };
 
 __device__ __forceinline__ Tuple make_tuple_(const SweepArgs& a, int64_t tau) {
@@ -142,6 +169,10 @@ __device__ __forceinline__ Tuple make_tuple_(const SweepArgs& a, int64_t tau) {
   q.z = mk(a.E[q.e], a.eta);
   q.sig = a.sigma + q.e * a.P;
   q.eps_r = a.eps ? a.eps + q.r * (int64_t)a.L * a.N : nullptr;
+  q.phi_s = q.phi_e = nullptr;
+  q.hs = 0;
+  q.he = 2 * a.L - 1;
+  q.g1 = true;
   return q;
 }
 
@@ -178,7 +209,7 @@ __device__ __forceinline__ void sub_mode_sum(cx<T> (&A)[S][C], const double* phi
 }
 
 // Assemble M_h into the register tile (padded with the identity).
-//   L half (h even, h > 0): M = z - eps - t^2 K            (K = g of R_{i-1})
+//   L half (h even, h > hs): M = z - eps - t^2 K           (K = g of R_{i-1})
 //   R half (h odd):         M = z - eps - t^2 B'^T K B'    (K = g of L_i)
 // where (B'^T K B')[r][c] = sum of K over the neighbour rows of r and the
 // neighbour columns of c; the column sums go through the wave's LDS scratch.
@@ -214,7 +245,7 @@ __device__ __forceinline__ uint32_t build_M(cx<T> (&A)[S][C], const SweepArgs& a
       for (int s = 0; s < S; ++s) {
         const int r = lane + 64 * s;
         cx<double> v = mk(0.0, 0.0);
-        if (h > 0 && r < n && c < n) v = cscale(ldg(K + (size_t)c * NP + r), mt2);
+        if (h > q.hs && r < n && c < n) v = cscale(ldg(K + (size_t)c * NP + r), mt2);
         if (r == c) v = cadd(v, mk(dre[s], r < n ? q.z.im : 0.0));
         A[s][j] = mk<T>((T)v.re, (T)v.im);
       }
@@ -248,8 +279,9 @@ __device__ __forceinline__ uint32_t build_M(cx<T> (&A)[S][C], const SweepArgs& a
       wave_sync_lds();
     }
   }
-  if (h == 0) sub_mode_sum<T, NW, S, C>(A, a.phi, q.sig, a.P, n);
-  if (h == 2 * a.L - 1) sub_mode_sum<T, NW, S, C>(A, a.phi + (size_t)a.P * NP, q.sig, a.P, n);
+  if (h == q.hs) sub_mode_sum<T, NW, S, C>(A, q.phi_s ? q.phi_s : a.phi, q.sig, a.P, n);
+  if (h == q.he)
+    sub_mode_sum<T, NW, S, C>(A, q.phi_e ? q.phi_e : a.phi + (size_t)a.P * NP, q.sig, a.P, n);
   // vacancies: their rows and columns become the identity's, so the inverse
   // is that of the lattice without them (the caller zeroes their own
   // diagonal entries of the inverse)
@@ -296,7 +328,7 @@ __device__ __forceinline__ cx<double> m_entry(const SweepArgs& a, const Tuple& q
   if (r == c) v = mk(q.z.re - (eps_slice ? eps_slice[half_row(r, e)] : 0.0), q.z.im);
   const double mt2 = -(a.t * a.t);
   if (!(h & 1)) {
-    if (h > 0) v = cadd(v, cscale(ldg(K + (size_t)c * NP + r), mt2));
+    if (h > q.hs) v = cadd(v, cscale(ldg(K + (size_t)c * NP + r), mt2));
   } else {
     const int nL = half_size(a.N, e ^ 1);
     const int r0 = nb_lo(r, e), r1 = nb_hi(r, e), c0 = nb_lo(c, e), c1 = nb_hi(c, e);
@@ -308,8 +340,8 @@ __device__ __forceinline__ cx<double> m_entry(const SweepArgs& a, const Tuple& q
     v = cadd(v, cscale(acc, mt2));
   }
   const double* phi = nullptr;
-  if (h == 0) phi = a.phi;
-  if (h == 2 * a.L - 1) phi = a.phi + (size_t)a.P * NP;
+  if (h == q.hs) phi = q.phi_s ? q.phi_s : a.phi;
+  if (h == q.he) phi = q.phi_e ? q.phi_e : a.phi + (size_t)a.P * NP;
   if (phi) {
     for (int p = 0; p < a.P; ++p) {
       const double f = phi[(size_t)p * NP + r] * phi[(size_t)p * NP + c];
@@ -352,7 +384,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
   const int w = wave_id();
   const int e = half_parity(h, a.parity);
   const int n = half_size(a.N, e);
-  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const int n1 = half_size(a.N, half_parity(q.hs, a.parity));
   uint32_t dkey;  // high word of max_k |E - eps_{h,k}| | vacancy bit (wave-uniform)
   if constexpr (sizeof(TJ) == sizeof(double)) {
     dkey = build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
@@ -365,7 +397,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     }
     // (a vacancy's diagonal entry is zeroed by the store)
     store_unpermuted<double, double, NW, S, C>(
-        A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout, h == 0 ? G1out : nullptr,
+        A, n, f, sm.wbuf, sm.pivrow, sm.pinv, Kout, h == q.hs ? G1out : nullptr,
         (dkey >> 31) ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr, e);
   } else {
     cx<float> AJ[S][C];
@@ -382,7 +414,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     // refinement keeps the identity's 1 there until it has converged
     store_unpermuted<float, double, NW, S, C>(
         AJ, n, f, reinterpret_cast<cx<float>*>(sm.wbuf), sm.pivrow, sm.pinv, Kout,
-        (h == 0 && !REFINE) ? G1out : nullptr,
+        (h == q.hs && !REFINE) ? G1out : nullptr,
         (!REFINE && (dkey >> 31)) ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr, e);
   }
   [[maybe_unused]] const bool vac = (dkey >> 31) != 0;  // block-uniform: every wave holds every row
@@ -407,6 +439,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
     const int lane = lane_id();
     bool converged = false;
     double rprev = 0.0;
+    unsigned upd = 0;
     for (int it = 0; it < 4; ++it) {
       {
         const Tuple& qq = q;
@@ -448,6 +481,7 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
       gemm_regs<double, NW, S, C, KC>(A, n, fa, fb, sm.As, sm.Bs);
       store_regs<double, double, NW, S, C>(A, n, n, Kout);
       __syncthreads();
+      ++upd;
       if (rmax < 1e-8) {   // the next residual is below n rmax^2 < n * 1e-16
         converged = true;
         break;
@@ -455,6 +489,11 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
       rprev = rmax;
     }
     const bool fallback = !converged;
+    if (threadIdx.x == 0) {
+      sm.rf[0] += 1u;
+      sm.rf[1] += upd;
+      sm.rf[2] += fallback ? 1u : 0u;
+    }
     if (fallback) {
       build_M<double, NW, S, C>(A, a, q, h, Kprev, sm.wbuf + w * NP);
       const double f = tile_scale<double, NW, S, C>(A, reinterpret_cast<uint32_t*>(sm.red));
@@ -468,12 +507,12 @@ __device__ __forceinline__ void half_step(const SweepArgs& a, const Tuple& q, in
       zero_vacant_diag<NP>(a, q, h, Kout, nullptr);
       __syncthreads();
     }
-    if (h == 0) {
+    if (h == q.hs) {
       for (int i = threadIdx.x; i < NP * NP; i += NW * 64) stg(G1out + i, ldg(Kout + i));
       __syncthreads();
     }
   }
-  if (h > 0) {
+  if (h > q.hs && q.g1) {
     // G1_h = (G1_{h-1} C_{h-1}) g_h on the matrix cores; g_h is complex
     // symmetric, so it is read transposed (rows contiguous)
     const double t = a.t;
@@ -535,7 +574,9 @@ __device__ __forceinline__ uint32_t mgj_build(MgjTile<T>& D, const SweepArgs& a,
   const int nL = half_size(a.N, e ^ 1);
   const double mt2 = -(a.t * a.t);
   const double* eps_slice = q.eps_r ? q.eps_r + (int64_t)(h >> 1) * a.N : nullptr;
-  const double* ph = (h == 0) ? a.phi : (h == 2 * a.L - 1) ? a.phi + (size_t)a.P * NP : nullptr;
+  const double* ph = (h == q.hs)   ? (q.phi_s ? q.phi_s : a.phi)
+                     : (h == q.he) ? (q.phi_e ? q.phi_e : a.phi + (size_t)a.P * NP)
+                                   : nullptr;
   K = opaque_uniform(K);
   const int c = 16 * w + li;
   const int c0 = nb_lo(c, e), c1 = nb_hi(c, e);
@@ -575,7 +616,7 @@ __device__ __forceinline__ uint32_t mgj_build(MgjTile<T>& D, const SweepArgs& a,
       cx<double> x = mk((r == c) ? 1.0 : 0.0, 0.0);
       if (r < n && c < n) {
         x = mk(0.0, 0.0);
-        if (h > 0) {
+        if (h > q.hs) {
           if (!rhalf) {
             x = cscale(ldg(K + (size_t)r * NP + c), mt2);
           } else {
@@ -653,12 +694,12 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
   static_assert(NP == 8 * 16, "matrix-core tile is the (8, 2, 16) tiling");
   const int e = half_parity(h, a.parity);
   const int n = half_size(a.N, e);
-  const int n1 = half_size(a.N, half_parity(0, a.parity));
+  const int n1 = half_size(a.N, half_parity(q.hs, a.parity));
   uint32_t dkey;
   if constexpr (sizeof(TJ) == sizeof(double))
-    dkey = mgj_inverse_to<double>(a, q, h, Kprev, Kout, h == 0 ? G1out : nullptr, sm, ms64);
+    dkey = mgj_inverse_to<double>(a, q, h, Kprev, Kout, h == q.hs ? G1out : nullptr, sm, ms64);
   else
-    dkey = mgj_inverse_to<float>(a, q, h, Kprev, Kout, (h == 0 && !REFINE) ? G1out : nullptr, sm,
+    dkey = mgj_inverse_to<float>(a, q, h, Kprev, Kout, (h == q.hs && !REFINE) ? G1out : nullptr, sm,
                                  *reinterpret_cast<MgjSmem<float>*>(&ms64),
                                  REFINE ? Mbuf : nullptr);
   const bool vac = (dkey >> 31) != 0;  // block-uniform
@@ -672,7 +713,7 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
     if (dkey < mag_hi(kChiralWindow * fabs(a.t))) sm.ksum_c += km;
   }
   if (!REFINE && vac) {
-    zero_vacant_diag<NP>(a, q, h, Kout, h == 0 ? G1out : nullptr);
+    zero_vacant_diag<NP>(a, q, h, Kout, h == q.hs ? G1out : nullptr);
     __syncthreads();
   }
   if constexpr (REFINE) {
@@ -684,6 +725,7 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
     // inverted again by the FP64 Gauss-Jordan.
     bool converged = false;
     double rprev = 0.0;
+    unsigned upd = 0;
     for (int it = 0; it < 4; ++it) {
       double lmax = 0.0;
       {
@@ -714,11 +756,17 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
         gemm_mfma<NW, NP>(n, n, n, fa, fb, epi);
       }
       __syncthreads();
+      ++upd;
       if (rmax < 1e-8) {  // the next residual is below n rmax^2 < n * 1e-16
         converged = true;
         break;
       }
       rprev = rmax;
+    }
+    if (threadIdx.x == 0) {
+      sm.rf[0] += 1u;
+      sm.rf[1] += upd;
+      sm.rf[2] += converged ? 0u : 1u;
     }
     if (!converged) {
       (void)mgj_inverse_to<double>(a, q, h, Kprev, Kout, nullptr, sm, ms64);
@@ -728,12 +776,12 @@ __device__ __forceinline__ void half_step_mgj(const SweepArgs& a, const Tuple& q
       zero_vacant_diag<NP>(a, q, h, Kout, nullptr);
       __syncthreads();
     }
-    if (h == 0) {
+    if (h == q.hs) {
       for (int i = threadIdx.x; i < NP * NP; i += NW * 64) stg(G1out + i, ldg(Kout + i));
       __syncthreads();
     }
   }
-  if (h > 0) {
+  if (h > q.hs && q.g1) {
     // G1_h = (G1_{h-1} C_{h-1}) g_h on the matrix cores (g_h read transposed)
     const double t = a.t;
     const cx<double>* G1r = opaque_uniform(G1in);

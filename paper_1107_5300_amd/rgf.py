@@ -154,6 +154,41 @@ def conductance_noalloc(ribbon, energies, eps=None, n_real=1, precision="fp64",
     return T
 
 
+def conductance_segments(ribbon, energies, eps=None, n_real=1, n_segments=0, workspace=None,
+                         return_status=False, return_segments=False, out=None):
+    """The conductance of `conductance` (FP64) with each tuple's recursion
+    split into segments along the ribbon length, solved on separate
+    workgroups and joined (librgf rgf_conductance_segments): for batches of
+    tuples too small to fill the GPU. n_segments = 0 picks the count."""
+    _need(energies, "energies")
+    nE = energies.numel()
+    dev = energies.device
+    if eps is not None:
+        if eps.dim() == 2:
+            eps = eps.unsqueeze(0)
+        _need(eps, "eps", (eps.shape[0], ribbon.L, ribbon.N))
+        n_real = eps.shape[0]
+    d = ribbon.desc()
+    L = _L.lib()
+    nbytes = L.rgf_segments_workspace_bytes(ctypes.byref(d), nE, int(n_real), int(n_segments))
+    if nbytes == 0:
+        msg = L.rgf_last_error_message().decode(errors="replace")
+        raise _L.RGFError(_L.RGF_ERR_INVALID_ARG, msg)
+    ws = _workspace(workspace, nbytes, dev)
+    T = out if out is not None else torch.empty((int(n_real), nE), dtype=torch.float64, device=dev)
+    st = torch.empty((int(n_real), nE), dtype=torch.int32, device=dev)
+    G = ctypes.c_int32()
+    _L.check(L.rgf_conductance_segments(ctypes.byref(d), _vp(energies), nE, _vp(eps),
+                                        int(n_real), int(n_segments), _vp(T), _vp(st),
+                                        ctypes.byref(G), _vp(ws), ws.numel(), _stream()))
+    res = (T,)
+    if return_status:
+        res += (st,)
+    if return_segments:
+        res += (G.value,)
+    return res[0] if len(res) == 1 else res
+
+
 def conductance_batched(ribbons, energies, eps_list=None, n_real=1, precision="fp64",
                         workspace=None, return_status=False):
     """Several ribbons (e.g. mixed widths) sharing one energy grid and one
@@ -397,6 +432,16 @@ class TileChoice(tuple):
         t = super().__new__(cls, (NW, S, C, per_cu))
         t.mgj = bool(mgj)
         return t
+
+
+def refine_stats(reset=False):
+    """Counters of the mixed mode's refinement on the current device (librgf
+    rgf_refine_stats): {"refined", "newton_updates", "fp64_reinversions"}
+    summed over the forward sweeps since the last reset; waits for the
+    current stream."""
+    c = (ctypes.c_uint64 * 3)()
+    _L.check(_L.lib().rgf_refine_stats(c, 1 if reset else 0, _stream()))
+    return {"refined": int(c[0]), "newton_updates": int(c[1]), "fp64_reinversions": int(c[2])}
 
 
 def version():
