@@ -205,8 +205,10 @@ int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev,
  * The result is T of Eq. (2) as from rgf_conductance (equal up to rounding);
  * the work is about 1.7x that of one sweep, spread over up to (2G - 1)
  * workgroups per tuple.
- *   n_segments   G; 0 picks G so that the tuples' items about fill the GPU
- *                (G = 1 when the tuples alone do); clamped to [1, min(L, 1024)]
+ *   n_segments   G; 0 picks the largest G whose n_tuples (2G - 1) workgroup
+ *                items run at once, at most sqrt(L / 4) (the joins run one
+ *                after another); G = 1 when the tuples alone fill the GPU.
+ *                Clamped to [1, min(L, 1024)]
  *   segments_out (may be NULL) receives the G used
  * Other arguments as for rgf_conductance, FP64 only, widths up to
  * RGF_TILE_MAX_WIDTH (RGF_ERR_UNSUPPORTED above). Tuples the accuracy guard

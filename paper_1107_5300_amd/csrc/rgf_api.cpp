@@ -348,7 +348,13 @@ int make_seg_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int n_seg
   const int occ = kernel_occupancy(seg_sweep_kernel(q.fwd.tile), q.fwd.tile.threads());
   const int64_t cap = (int64_t)ncu * occ;
   int64_t G = n_segments;
-  if (G == 0) G = nt > 0 ? (cap / std::max<int64_t>(nt, 1) + 2) / 2 : 1;  // items ~ the slots
+  // automatic: the most segments whose nt (2G - 1) items fit the slots at
+  // once, but no more than sqrt(L / 4): a tuple's latency is about 2L/G
+  // half-slice steps of its segments plus 8 (G - 1) for the joins
+  if (G == 0) {
+    G = nt > 0 ? (cap / std::max<int64_t>(nt, 1) + 1) / 2 : 1;
+    G = std::min<int64_t>(G, std::max<int64_t>(1, (int64_t)sqrt(d->length_l / 4.0)));
+  }
   G = std::max<int64_t>(1, std::min<int64_t>({G, (int64_t)d->length_l, 1024}));
   q.G = (int)G;
   const int64_t nitems = nt * (2 * G - 1);
