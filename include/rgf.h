@@ -230,15 +230,18 @@ int rgf_conductance_segments(const rgf_ribbon_desc* desc, const double* energies
  * onsite_eps_ev + eps_offsets[d] ([n_real][L_d][N_d]) and writes
  * T_out + T_offsets[d] ([n_real][n_energies]) and the same offset into
  * status_out (may be NULL). All ribbons share energies_ev, n_real and
- * precision. The ribbons run concurrently: each gets its own part of the
+ * precision. When every ribbon has at least as many tuples as the GPU has
+ * persistent workgroup slots for it, the ribbons run one after another on
+ * hip_stream (costliest first), each on the whole GPU, in one shared
+ * workspace. Otherwise they run concurrently: each gets its own part of the
  * workspace and a share of the persistent workgroups proportional to its
  * work (n^3 L per tuple, n = ceil(N/2)), and all but the costliest run on
  * library-owned streams (default priority, created once per device) that
  * are forked from hip_stream by an event and joined back to it before the
  * call's work ends, so the call stays stream-ordered and capturable (the
- * streams are created by the first call with several ribbons on a device,
- * which must not be made under stream capture). The workspace is the sum of
- * the ribbons' parts. With one ribbon this is rgf_conductance. */
+ * streams are created by the first concurrent call on a device, which must
+ * not be made under stream capture); the workspace is then the sum of the
+ * parts. With one ribbon this is rgf_conductance. */
 size_t rgf_batched_workspace_bytes(const rgf_ribbon_desc* descs, int32_t n_desc,
                                    int64_t n_energies, int64_t n_real,
                                    int precision);
