@@ -175,17 +175,18 @@ def lead_time_ms(Es, reps=5):
 
 
 def csrc_fingerprint():
-    """sha256 prefix over the translation unit of the forward sweep kernels
-    (csrc/rgf_forward.hip and every header it includes, transitively), the
-    rule the counter summaries under profiles/ record, so a counter figure
-    is only reported for the kernel code it was measured on."""
+    """sha256 prefix over the sources of the forward sweep kernels
+    (csrc/rgf_forward.hip and every header under csrc/ it includes,
+    transitively; the public ABI header is left out), the rule the counter
+    summaries under profiles/ record, so a counter figure is only reported
+    for the kernel code it was measured on."""
     import hashlib
     import re
     d = os.path.join(ROOT, "paper_1107_5300_amd", "csrc")
     todo, seen = [os.path.join(d, "rgf_forward.hip")], set()
     while todo:
         f = os.path.normpath(todo.pop())
-        if f in seen or not os.path.exists(f):
+        if f in seen or not os.path.exists(f) or os.path.dirname(f) != os.path.normpath(d):
             continue
         seen.add(f)
         with open(f) as fh:
