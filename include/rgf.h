@@ -199,23 +199,23 @@ int rgf_ldos(const rgf_ribbon_desc* desc, const double* energies_ev,
  * ribbon's ends). Every segment is solved on its own by the left-connected
  * sweep (corners G[a, b], G[b, b]) and, for all but the first, the same
  * sweep over the reversed segment (corner G[a, a]), each on a workgroup of
- * its own; the segments are then joined left to right by Dyson's equation
- * (Eq. (3)) across the inter-slice bonds, which also takes the closing
- * self-energies out again.
+ * its own; the segments are then joined pairwise in a tree of ceil(log2 G)
+ * levels by Dyson's equation (Eq. (3)) across the inter-slice bonds, which
+ * also takes the closing self-energies out again.
  * The result is T of Eq. (2) as from rgf_conductance (equal up to rounding);
  * the work is about 1.7x that of one sweep, spread over up to (2G - 1)
  * workgroups per tuple.
  *   n_segments   G; 0 picks the largest G whose n_tuples (2G - 1) workgroup
- *                items run at once, at most sqrt(L / 4) (the joins run one
- *                after another); G = 1 when the tuples alone fill the GPU.
- *                Clamped to [1, min(L, 1024)]
+ *                items run at once, with at least two slices per segment;
+ *                G = 1 when the tuples alone fill the GPU. Clamped to
+ *                [1, min(L, 1024)]
  *   segments_out (may be NULL) receives the G used
  * Other arguments as for rgf_conductance, FP64 only, widths up to
  * RGF_TILE_MAX_WIDTH (RGF_ERR_UNSUPPORTED above). Tuples the accuracy guard
  * rejects are recomputed by the whole-slice sweep, as in rgf_conductance.
  * The workspace is rgf_segments_workspace_bytes(desc, n_energies, n_real,
  * n_segments) bytes: per tuple and segment three ceil(N/2)^2 complex128
- * matrices (padded to the tile), six more per joining workgroup, the lead
+ * matrices (padded to the tile), eight more per joining workgroup, the lead
  * tables and a reversed copy of the on-site energies. */
 size_t rgf_segments_workspace_bytes(const rgf_ribbon_desc* desc, int64_t n_energies,
                                     int64_t n_real, int32_t n_segments);

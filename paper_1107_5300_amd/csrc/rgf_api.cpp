@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "rgf_internal.hpp"
+#include "rgf_segplan.hpp"
 
 namespace rgf {
 
@@ -349,16 +350,18 @@ int make_seg_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int n_seg
   const int64_t cap = (int64_t)ncu * occ;
   int64_t G = n_segments;
   // automatic: the most segments whose nt (2G - 1) items fit the slots at
-  // once, but no more than sqrt(L / 4): a tuple's latency is about 2L/G
-  // half-slice steps of its segments plus 8 (G - 1) for the joins
+  // once (a tuple's latency is about 2L/G half-slice steps of its segments
+  // plus 8 per level of the ceil(log2 G) levels of joins), at least two
+  // slices each
   if (G == 0) {
     G = nt > 0 ? (cap / std::max<int64_t>(nt, 1) + 1) / 2 : 1;
-    G = std::min<int64_t>(G, std::max<int64_t>(1, (int64_t)sqrt(d->length_l / 4.0)));
+    G = std::min<int64_t>(G, std::max<int64_t>(1, d->length_l / 2));
   }
   G = std::max<int64_t>(1, std::min<int64_t>({G, (int64_t)d->length_l, 1024}));
   q.G = (int)G;
   const int64_t nitems = nt * (2 * G - 1);
   q.sweep_grid = (int)std::max<int64_t>(1, std::min(cap, nitems));
+  q.merge_grid = (int)std::max<int64_t>(1, std::min(cap, nt * (G / 2)));
   q.join_grid = (int)std::max<int64_t>(1, std::min(cap, nt));
   // lead tables of the reversed ribbon: the part of its plan before the flags
   size_t off = align_up(q.fwd.total, 256);
@@ -369,11 +372,11 @@ int make_seg_plan(const rgf_ribbon_desc* d, int64_t nE, int64_t nreal, int n_seg
   q.off_mats = off;
   off = align_up(off + (size_t)nt * G * 3 * NP * NP * 16, 256);
   q.off_scratch = off;
-  off = align_up(off + (size_t)q.join_grid * 6 * NP * NP * 16, 256);
+  off = align_up(off + (size_t)q.merge_grid * 8 * NP * NP * 16, 256);
   q.off_kap = off;
-  off = align_up(off + (size_t)nt * 2 * G * 2 * 8, 256);
+  off = align_up(off + (size_t)nt * 3 * G * 2 * 8, 256);
   q.off_flag = off;
-  off = align_up(off + (size_t)nt * 2 * G * 4, 256);
+  off = align_up(off + (size_t)nt * 3 * G * 4, 256);
   q.total = off;
   *sp = q;
   return RGF_OK;

@@ -25,25 +25,31 @@
 //     reversed ribbon is an armchair ribbon of parity (parity + L) mod 2
 //     with the slices in reverse order), whose last g is Raa = G^k[a, a].
 //
-// The join (one workgroup per tuple) runs left to right. The joined part
-// has the corners Lfb = G[first, b], Lbb = G[b, b] (b = b_{k-1}, closed by
-// Lambda); the cut's row classes agree, so one Lambda serves both sides and
-// the bond is t I. Dyson's equation (Eq. (3)) with the perturbation
-// [[Lambda, -t], [-t, Lambda]] on (b, a_k) gives, by block elimination,
-//   Q    = (I + Lambda Lbb)^{-1}
-//   S    = I + Lambda Raa - t^2 Lbb Q Raa
-//   Y    = S^{-1} (Lambda Rab - t^2 Lbb Q Rab)
-//   Lfb' = t Lfb Q (Rab - Raa Y)
-//   Lbb' = Rbb - Rab^T Y                    (Rba = Rab^T: G is complex symmetric)
-// (with Lambda = 0 this is Lfb' = t Lfb (I - t^2 Raa Lbb)^{-1} Rab). After
-// the last segment Lfb = G_{1L} and Eq. (2) gives T, as in the sequential
-// sweep. Each item costs one segment sweep (the backward one without the G1
-// products); a join costs about six half-slice steps. The accuracy guard
-// sums the condition estimates of every inversion of the tuple; rejected
-// tuples are recomputed by the whole-slice sweep, as in rgf_conductance.
+// The joins run as a tree: at level l (l = 1, 2, ...) the part made of
+// segments [j 2^l, j 2^l + 2^(l-1)) merges with the part that follows it,
+// every (tuple, pair) on a workgroup of its own, so a tuple's G segments
+// are joined in ceil(log2 G) levels. A part has the corners Paa, Pab, Pbb
+// of its Green's function (Pba = Pab^T: G is complex symmetric) with both
+// ends closed by Lambda. At the cut between P's last half-slice b and Q's
+// first a the row classes agree, so one Lambda serves both sides and the
+// bond is t I. Dyson's equation (Eq. (3)) with the perturbation
+// [[Lambda, -t], [-t, Lambda]] on (b, a), solved by block elimination:
+//   Q1   = (I + Lambda Pbb)^{-1},   S = I + Lambda Qaa - t^2 Pbb Q1 Qaa
+//   Y    = S^{-1} (Lambda Qab - t^2 Pbb Q1 Qab)
+//   Rab  = t Pab Q1 (Qab - Qaa Y),  Rbb = Qbb - Qab^T Y
+//   Y2   = S^{-1} t (Pbb Q1 Lambda Pba - Pba)
+//   Raa  = Paa - Pab Q1 (Lambda Pba + t Qaa Y2)     (not for the leftmost part)
+// (with Lambda = 0, Rab = t Pab (I - t^2 Qaa Pbb)^{-1} Qab). After the last
+// level the part of all segments has Rab = G_{1L}, and Eq. (2) gives T as in
+// the sequential sweep. Each item costs one segment sweep (the backward one
+// without the G1 products); a merge costs about eight half-slice steps. The
+// accuracy guard sums the condition estimates of every inversion of the
+// tuple; rejected tuples are recomputed by the whole-slice sweep, as in
+// rgf_conductance.
 
 #include <string.h>
 
+#include "rgf_segplan.hpp"
 #include "rgf_sweep.hpp"
 
 namespace rgf {
@@ -54,10 +60,12 @@ namespace {
 struct SegArgs {
   int G;                   // segments per tuple: segment k holds slices [k L / G, (k + 1) L / G)
   const double* phi2;      // [2][P][NP] mode tables of the two row classes (class 0, class 1)
-  cx<double>* mats;        // [ntuples][G][3][NP*NP]: Rab, Rbb, Raa of each segment
-  cx<double>* scratch;     // [join grid][6][NP*NP]: the join's work matrices
-  double* kap;             // [ntuples][2G] (ksum, ksum_c) of each item, forward then backward
-  int* flag;               // [ntuples][2G] exact-zero pivot seen by the item
+  cx<double>* mats;        // [ntuples][G][3][NP*NP]: Rab, Rbb, Raa of each segment (of each
+                           // part after the merges, at the part's first segment)
+  cx<double>* scratch;     // [merge grid][8][NP*NP]: a merge's work matrices
+  double* kap;             // [ntuples][3G][2] (ksum, ksum_c): forward items, backward items,
+                           // merges (by the first segment of the right part)
+  int* flag;               // [ntuples][3G] exact-zero pivot seen by the item
   int64_t nitems;          // ntuples * (2G - 1)
 };
 
@@ -107,9 +115,9 @@ __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : 3) void rgf_seg_sweep_kernel
       half_step<double, false, NW, S, C>(A, q, h, K, K, G1, G1, nullptr, R, sm);
     if (threadIdx.x == 0) {
       const int slot = fwd ? k : g.G + k;
-      g.kap[(tau * 2 * g.G + slot) * 2] = sm.ksum;
-      g.kap[(tau * 2 * g.G + slot) * 2 + 1] = sm.ksum_c;
-      g.flag[tau * 2 * g.G + slot] = sm.flag;
+      g.kap[(tau * 3 * g.G + slot) * 2] = sm.ksum;
+      g.kap[(tau * 3 * g.G + slot) * 2 + 1] = sm.ksum_c;
+      g.flag[tau * 3 * g.G + slot] = sm.flag;
     }
     __syncthreads();
   }
@@ -147,124 +155,166 @@ __device__ __forceinline__ double invert_in_place(cx<double>* X, int n, cx<doubl
   return kap;
 }
 
-// Join the segments of each tuple (one workgroup per tuple) and evaluate
-// Eq. (2); flags the tuples the guard rejects for the whole-slice sweep.
+// Level `level` of the tree of joins: item (tuple, j) merges the part that
+// starts at segment j 2^level with the one at j 2^level + 2^(level-1),
+// writing the merged corners over the left part's.
+template <int NW, int S, int C>
+__global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : 3) void rgf_seg_merge_kernel(
+    SweepArgs a, SegArgs g, int level) {
+  constexpr int NP = NW * C;
+  constexpr size_t MAT = (size_t)NP * NP;
+  __shared__ SweepSmem<NW, S, C> sm;
+  const double t = a.t, t2 = a.t * a.t;
+  const int half = 1 << (level - 1), span = 2 * half;
+  const int npairs = (g.G - half + span - 1) / span;   // pairs whose right part exists
+  cx<double>* X = g.scratch + (size_t)blockIdx.x * 8 * MAT;
+  cx<double>* Lam = X;              // Lambda
+  cx<double>* Q1 = X + MAT;         // I + Lambda Pbb, then Q1
+  cx<double>* Q1Qaa = X + 2 * MAT;
+  cx<double>* Zb = X + 3 * MAT;     // Q1 Qab, then Z = Q1 Qab - Q1 Qaa Y
+  cx<double>* Sb = X + 4 * MAT;     // Pbb Q1 Qaa, then S, then S^{-1}
+  cx<double>* Yb = X + 5 * MAT;     // Pbb Q1 Qab, then the right-hand side, then Y
+  cx<double>* U = X + 6 * MAT;      // Lambda Pba, then Lambda Pba + t Qaa Y2
+  cx<double>* V = X + 7 * MAT;      // Q1 Lambda Pba, then the right-hand side of Y2, Y2, Q1 (..)
+  auto delta = [](int r, int c) { return (r == c) ? 1.0 : 0.0; };
+  for (int64_t it = blockIdx.x; it < a.ntuples * (int64_t)npairs; it += gridDim.x) {
+    const int64_t tau = it / npairs;
+    const int left = (int)(it - tau * npairs) * span, right = left + half;
+    const int qend = min(right + half, g.G);        // Q holds segments [right, qend)
+    const Tuple q = make_tuple_(a, tau);
+    cx<double>* Pab = seg_mat(g, tau, left, 0, MAT);
+    cx<double>* Pbb = seg_mat(g, tau, left, 1, MAT);
+    cx<double>* Paa = seg_mat(g, tau, left, 2, MAT);
+    const cx<double>* Qab = seg_mat(g, tau, right, 0, MAT);
+    const cx<double>* Qbb = seg_mat(g, tau, right, 1, MAT);
+    const cx<double>* Qaa = seg_mat(g, tau, right, 2, MAT);
+    const int ha = 2 * seg_bound(g, a.L, right);
+    const int ec = half_parity(ha, a.parity);
+    const int n = half_size(a.N, ec);      // rows at the cut (both sides)
+    const int npa = half_size(a.N, half_parity(2 * seg_bound(g, a.L, left), a.parity));
+    const int nqb = half_size(a.N, half_parity(2 * seg_bound(g, a.L, qend) - 1, a.parity));
+    const double* ph = g.phi2 + (size_t)ec * a.P * NP;
+    cx<double> R[S][C];
+    if (threadIdx.x == 0) sm.flag = 0;
+    __syncthreads();
+    auto mul = [&](const cx<double>* A_, const cx<double>* B_, int nr, int nc, int nk,
+                   auto epi) {
+      auto fa = [&](int r, int kk) -> cx<double> { return ldg(A_ + (size_t)kk * NP + r); };
+      auto fb = [&](int kk, int c) -> cx<double> { return ldg(B_ + (size_t)c * NP + kk); };
+      gemm_mfma<NW, NP>(nr, nc, nk, fa, fb, epi);
+      __syncthreads();
+    };
+    auto put = [](cx<double>* D) {
+      return [D](int r, int c, cx<double> v, bool ok) {
+        if (ok) stg(D + (size_t)c * NP + r, v);
+      };
+    };
+    // Lambda = Phi diag(sigma) Phi^T of the cut's row class
+    {
+      auto fa = [&](int r, int p) -> cx<double> { return cscale(q.sig[p], ph[(size_t)p * NP + r]); };
+      auto fb = [&](int p, int c) -> cx<double> { return mk(ph[(size_t)p * NP + c], 0.0); };
+      gemm_mfma<NW, NP>(n, n, a.P, fa, fb, put(Lam));
+      __syncthreads();
+    }
+    double ksum = 0.0;
+    // Q1 = (I + Lambda Pbb)^{-1}
+    mul(Lam, Pbb, n, n, n, [&](int r, int c, cx<double> v, bool ok) {
+      if (ok) stg(Q1 + (size_t)c * NP + r, mk(delta(r, c) + v.re, v.im));
+    });
+    ksum += invert_in_place<NW, S, C>(Q1, n, R, sm);
+    mul(Q1, Qaa, n, n, n, put(Q1Qaa));
+    mul(Q1, Qab, n, nqb, n, put(Zb));
+    // S = I + Lambda Qaa - t^2 Pbb Q1 Qaa, inverted
+    mul(Pbb, Q1Qaa, n, n, n, put(Sb));
+    mul(Lam, Qaa, n, n, n, [&](int r, int c, cx<double> v, bool ok) {
+      if (!ok) return;
+      const cx<double> w = ldg(Sb + (size_t)c * NP + r);
+      stg(Sb + (size_t)c * NP + r, mk(delta(r, c) + v.re - t2 * w.re, v.im - t2 * w.im));
+    });
+    ksum += invert_in_place<NW, S, C>(Sb, n, R, sm);
+    // Y = S^{-1} (Lambda Qab - t^2 Pbb Q1 Qab)
+    mul(Pbb, Zb, n, nqb, n, put(Yb));
+    mul(Lam, Qab, n, nqb, n, [&](int r, int c, cx<double> v, bool ok) {
+      if (!ok) return;
+      const cx<double> w = ldg(Yb + (size_t)c * NP + r);
+      stg(Yb + (size_t)c * NP + r, mk(v.re - t2 * w.re, v.im - t2 * w.im));
+    });
+    mul(Sb, Yb, n, nqb, n, put(Yb));
+    if (left > 0) {
+      // Raa = Paa - Pab Q1 (Lambda Pba + t Qaa Y2),
+      // Y2 = S^{-1} t (Pbb Q1 Lambda Pba - Pba)
+      {
+        auto fa = [&](int r, int kk) -> cx<double> { return ldg(Lam + (size_t)kk * NP + r); };
+        auto fb = [&](int kk, int c) -> cx<double> { return ldg(Pab + (size_t)kk * NP + c); };
+        gemm_mfma<NW, NP>(n, npa, n, fa, fb, put(U));   // Lambda Pba (Pba[k][c] = Pab[c][k])
+        __syncthreads();
+      }
+      mul(Q1, U, n, npa, n, put(V));
+      mul(Pbb, V, n, npa, n, [&](int r, int c, cx<double> v, bool ok) {
+        if (!ok) return;
+        const cx<double> pba = ldg(Pab + (size_t)r * NP + c);   // Pba[r][c]
+        stg(V + (size_t)c * NP + r, mk(t * (v.re - pba.re), t * (v.im - pba.im)));
+      });
+      mul(Sb, V, n, npa, n, put(V));                             // Y2
+      mul(Qaa, V, n, npa, n, [&](int r, int c, cx<double> v, bool ok) {
+        if (ok) stg(U + (size_t)c * NP + r, cadd(ldg(U + (size_t)c * NP + r), cscale(v, t)));
+      });
+      mul(Q1, U, n, npa, n, put(V));
+      mul(Pab, V, npa, npa, n, [&](int r, int c, cx<double> v, bool ok) {
+        if (ok) stg(Paa + (size_t)c * NP + r, csub(ldg(Paa + (size_t)c * NP + r), v));
+      });
+    }
+    // Z = Q1 Qab - Q1 Qaa Y, then Rbb = Qbb - Qab^T Y (over Pbb), Rab = t Pab Z (over Pab)
+    mul(Q1Qaa, Yb, n, nqb, n, [&](int r, int c, cx<double> v, bool ok) {
+      if (ok) stg(Zb + (size_t)c * NP + r, csub(ldg(Zb + (size_t)c * NP + r), v));
+    });
+    {
+      auto fa = [&](int r, int kk) -> cx<double> { return ldg(Qab + (size_t)r * NP + kk); };
+      auto fb = [&](int kk, int c) -> cx<double> { return ldg(Yb + (size_t)c * NP + kk); };
+      auto epi = [&](int r, int c, cx<double> v, bool ok) {
+        if (ok) stg(Pbb + (size_t)c * NP + r, csub(ldg(Qbb + (size_t)c * NP + r), v));
+      };
+      gemm_mfma<NW, NP>(nqb, nqb, n, fa, fb, epi);
+      __syncthreads();
+    }
+    mul(Pab, Zb, npa, nqb, n, [&](int r, int c, cx<double> v, bool ok) {
+      if (ok) stg(Pab + (size_t)c * NP + r, cscale(v, t));
+    });
+    if (threadIdx.x == 0) {
+      g.kap[(tau * 3 * g.G + 2 * g.G + right) * 2] = ksum;
+      g.kap[(tau * 3 * g.G + 2 * g.G + right) * 2 + 1] = 0.0;
+      g.flag[tau * 3 * g.G + 2 * g.G + right] = sm.flag;
+    }
+    __syncthreads();
+  }
+}
+
+// Eq. (2) from the merged part (one workgroup per tuple) and the status of
+// the tuple; flags the tuples the guard rejects for the whole-slice sweep.
 template <int NW, int S, int C>
 __global__ __launch_bounds__(NW * 64, NW >= 8 ? 2 : 3) void rgf_seg_join_kernel(
     SweepArgs a, SweepArgs ar, SegArgs g) {
   constexpr int NP = NW * C;
   constexpr size_t MAT = (size_t)NP * NP;
   __shared__ SweepSmem<NW, S, C> sm;
-  const double t = a.t, t2 = a.t * a.t;
-  const int n1 = half_size(a.N, half_parity(0, a.parity));
-  cx<double>* X = g.scratch + (size_t)blockIdx.x * 6 * MAT;
-  cx<double>* Lam = X;             // Lambda, later Y
-  cx<double>* Qb = X + MAT;        // I + Lambda Lbb, then Q
-  cx<double>* QRaa = X + 2 * MAT;  // Q Raa
-  cx<double>* QRab = X + 3 * MAT;  // Q Rab, then Rab - Raa Y
-  cx<double>* Sb = X + 4 * MAT;    // Lbb Q Raa, then S, then S^{-1}
-  cx<double>* Rh = X + 5 * MAT;    // the right-hand side of Y
-  auto delta = [](int r, int c) { return (r == c) ? 1.0 : 0.0; };
   for (int64_t tau = blockIdx.x; tau < a.ntuples; tau += gridDim.x) {
     const Tuple q = make_tuple_(a, tau);
-    cx<double>* Lfb = seg_mat(g, tau, 0, 0, MAT);
-    cx<double>* Lbb = seg_mat(g, tau, 0, 1, MAT);
     cx<double> R[S][C];
     double ksum = 0.0, ksum_c = 0.0;
     int flag = 0;
-    for (int i = 0; i < 2 * g.G; ++i) {
-      if (i == g.G) continue;  // segment 0 has no backward item
-      ksum += g.kap[(tau * 2 * g.G + i) * 2];
-      ksum_c += g.kap[(tau * 2 * g.G + i) * 2 + 1];
-      flag |= g.flag[tau * 2 * g.G + i];
+    for (int i = 0; i < 3 * g.G; ++i) {
+      if (i == g.G || i == 2 * g.G) continue;  // no backward item for segment 0, no merge at 0
+      ksum += g.kap[(tau * 3 * g.G + i) * 2];
+      ksum_c += g.kap[(tau * 3 * g.G + i) * 2 + 1];
+      flag |= g.flag[tau * 3 * g.G + i];
     }
-    if (threadIdx.x == 0) sm.flag = 0;
-    __syncthreads();
-    for (int k = 1; k < g.G; ++k) {
-      const cx<double>* Rab = seg_mat(g, tau, k, 0, MAT);
-      const cx<double>* Rbb = seg_mat(g, tau, k, 1, MAT);
-      const cx<double>* Raa = seg_mat(g, tau, k, 2, MAT);
-      const int ha = 2 * seg_bound(g, a.L, k), hb = 2 * seg_bound(g, a.L, k + 1) - 1;
-      const int ea = half_parity(ha, a.parity);
-      const int n = half_size(a.N, ea);   // rows of b_{k-1} and a_k (the same class)
-      const int nb = half_size(a.N, half_parity(hb, a.parity));
-      const double* ph = g.phi2 + (size_t)ea * a.P * NP;
-      // Lambda = Phi diag(sigma) Phi^T of the cut's row class
-      {
-        auto fa = [&](int r, int p) -> cx<double> { return cscale(q.sig[p], ph[(size_t)p * NP + r]); };
-        auto fb = [&](int p, int c) -> cx<double> { return mk(ph[(size_t)p * NP + c], 0.0); };
-        auto epi = [&](int r, int c, cx<double> v, bool ok) {
-          if (ok) stg(Lam + (size_t)c * NP + r, v);
-        };
-        gemm_mfma<NW, NP>(n, n, a.P, fa, fb, epi);
-      }
-      __syncthreads();
-      auto mul = [&](const cx<double>* A_, const cx<double>* B_, int nr, int nc, int nk,
-                     auto epi) {
-        auto fa = [&](int r, int kk) -> cx<double> { return ldg(A_ + (size_t)kk * NP + r); };
-        auto fb = [&](int kk, int c) -> cx<double> { return ldg(B_ + (size_t)c * NP + kk); };
-        gemm_mfma<NW, NP>(nr, nc, nk, fa, fb, epi);
-        __syncthreads();
-      };
-      // Q = (I + Lambda Lbb)^{-1}
-      mul(Lam, Lbb, n, n, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(Qb + (size_t)c * NP + r, mk(delta(r, c) + v.re, v.im));
-      });
-      ksum += invert_in_place<NW, S, C>(Qb, n, R, sm);
-      // Q Raa, Q Rab
-      mul(Qb, Raa, n, n, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(QRaa + (size_t)c * NP + r, v);
-      });
-      mul(Qb, Rab, n, nb, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(QRab + (size_t)c * NP + r, v);
-      });
-      // S = I + Lambda Raa - t^2 Lbb (Q Raa)
-      mul(Lbb, QRaa, n, n, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(Sb + (size_t)c * NP + r, v);
-      });
-      mul(Lam, Raa, n, n, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (!ok) return;
-        const cx<double> w = ldg(Sb + (size_t)c * NP + r);
-        stg(Sb + (size_t)c * NP + r, mk(delta(r, c) + v.re - t2 * w.re, v.im - t2 * w.im));
-      });
-      ksum += invert_in_place<NW, S, C>(Sb, n, R, sm);
-      // right-hand side Lambda Rab - t^2 Lbb (Q Rab)
-      mul(Lbb, QRab, n, nb, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(Rh + (size_t)c * NP + r, v);
-      });
-      mul(Lam, Rab, n, nb, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (!ok) return;
-        const cx<double> w = ldg(Rh + (size_t)c * NP + r);
-        stg(Rh + (size_t)c * NP + r, mk(v.re - t2 * w.re, v.im - t2 * w.im));
-      });
-      // Y = S^{-1} (right-hand side), into Lambda's buffer
-      mul(Sb, Rh, n, nb, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(Lam + (size_t)c * NP + r, v);
-      });
-      // Lbb' = Rbb - Rab^T Y (Lbb is not read again in this step)
-      {
-        auto fa = [&](int r, int kk) -> cx<double> { return ldg(Rab + (size_t)r * NP + kk); };
-        auto fb = [&](int kk, int c) -> cx<double> { return ldg(Lam + (size_t)c * NP + kk); };
-        auto epi = [&](int r, int c, cx<double> v, bool ok) {
-          if (ok) stg(Lbb + (size_t)c * NP + r, csub(ldg(Rbb + (size_t)c * NP + r), v));
-        };
-        gemm_mfma<NW, NP>(nb, nb, n, fa, fb, epi);
-        __syncthreads();
-      }
-      // Z = Q Rab - Q Raa Y (in place), then Lfb' = t Lfb Z
-      mul(QRaa, Lam, n, nb, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(QRab + (size_t)c * NP + r, csub(ldg(QRab + (size_t)c * NP + r), v));
-      });
-      mul(Lfb, QRab, n1, nb, n, [&](int r, int c, cx<double> v, bool ok) {
-        if (ok) stg(Lfb + (size_t)c * NP + r, cscale(v, t));
-      });
-    }
-    // Eq. (2) from G_{1L} = Lfb (the trace's scratch: Lambda's buffer)
-    const double T = trace_T<NW, S, C>(a, q, Lfb, Lam, R, sm);
+    // G_{1L} = Rab of the part of all segments (the trace's scratch: its Rbb)
+    const double T = trace_T<NW, S, C>(a, q, seg_mat(g, tau, 0, 0, MAT),
+                                       seg_mat(g, tau, 0, 1, MAT), R, sm);
     if (threadIdx.x == 0) {
       int st = a.lstat[q.e];
       if (st == RGF_TUPLE_OK && ill_conditioned(ksum, ksum_c)) st = RGF_TUPLE_ILL_CONDITIONED;
-      if (st == RGF_TUPLE_OK && (flag || sm.flag)) st = RGF_TUPLE_SINGULAR;
+      if (st == RGF_TUPLE_OK && flag) st = RGF_TUPLE_SINGULAR;
       if (st == RGF_TUPLE_OK && !isfinite(T)) st = RGF_TUPLE_NONFINITE;
       if (st == RGF_TUPLE_OK && !t_in_range(T, a.P)) st = RGF_TUPLE_OUT_OF_RANGE;
       a.T_out[tau] = (st == RGF_TUPLE_OK) ? T : __builtin_nan("");
@@ -291,11 +341,15 @@ __global__ void reverse_slices_kernel(const double* in, double* out, int64_t nre
 struct SegEntry {
   int NW, S, C;
   void (*sweep)(SweepArgs, SweepArgs, SegArgs);
+  void (*merge)(SweepArgs, SegArgs, int);
   void (*join)(SweepArgs, SweepArgs, SegArgs);
 };
 
-#define RGF_SEG_ENTRY(NW, S, C) \
-  { NW, S, C, rgf_seg_sweep_kernel<NW, S, C>, rgf_seg_join_kernel<NW, S, C> }
+#define RGF_SEG_ENTRY(NW, S, C)                                                 \
+  {                                                                             \
+    NW, S, C, rgf_seg_sweep_kernel<NW, S, C>, rgf_seg_merge_kernel<NW, S, C>,   \
+        rgf_seg_join_kernel<NW, S, C>                                           \
+  }
 
 const SegEntry kSeg[] = {
     RGF_SEG_ENTRY(1, 1, 8),  RGF_SEG_ENTRY(1, 1, 16), RGF_SEG_ENTRY(2, 1, 16),
@@ -382,6 +436,13 @@ hipError_t launch_segments(const SegPlan& sp, const double* E, const double* eps
   g.nitems = p.ntuples * (2 * (int64_t)sp.G - 1);
   hipLaunchKernelGGL(f->sweep, dim3(sp.sweep_grid), dim3(f->NW * 64), 0, s, a, ar, g);
   if ((err = hipGetLastError()) != hipSuccess) return err;
+  for (int level = 1; (1 << (level - 1)) < sp.G; ++level) {
+    const int half = 1 << (level - 1);
+    const int64_t items = p.ntuples * (int64_t)((sp.G - half + 2 * half - 1) / (2 * half));
+    const int grid = (int)std::min<int64_t>(items, sp.merge_grid);
+    hipLaunchKernelGGL(f->merge, dim3(grid), dim3(f->NW * 64), 0, s, a, g, level);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
   hipLaunchKernelGGL(f->join, dim3(sp.join_grid), dim3(f->NW * 64), 0, s, a, ar, g);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if (!a.fb_flags) return hipSuccess;
