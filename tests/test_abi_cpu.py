@@ -123,6 +123,27 @@ def test_forward_kernels_use_no_scratch():
     assert not bad, f"forward kernels with scratch / VGPR spills: {bad}"
 
 
+def test_gradient_and_ldos_kernel_spills_bounded():
+    """The FP64 gradient and LDOS kernels: no scratch in any tiling but the
+    8-wave two-slot ones, where the spill stays under 64 registers (in the
+    compiled code most reloads sit outside the sweep loops; the rest are at
+    most 8 per half-slice beside 128 to 192 matrix instructions)."""
+    from paper_1107_5300_amd import _lib as L
+    path = os.path.join(os.path.dirname(L.LIB_PATH), "_build", "kernel_resources.txt")
+    if not os.path.exists(path):
+        pytest.skip("no resource report (library not built in this tree)")
+    with open(path) as fh:
+        rows = [ln.rstrip("\n").split("\t") for ln in fh][1:]
+    ks = [r for r in rows if ("rgf_grad_kernel<double" in r[0] or "rgf_ldos_kernel<double" in r[0])]
+    assert len(ks) >= 20, "report lists too few gradient / LDOS kernels"
+    for r in ks:
+        two_slot = ", 8, 2," in r[0]
+        if not two_slot:
+            assert r[3] == "0" and r[4] == "0", r
+        else:
+            assert int(r[4]) <= 64 and int(r[3]) <= 256, r
+
+
 def test_widest_supported_and_first_unsupported_width():
     """N = 512 is the widest ribbon (two blocks of at most 128 rows per
     half-slice); N = 513 reports RGF_ERR_UNSUPPORTED before anything is
