@@ -247,13 +247,19 @@ __device__ __forceinline__ void gj_step(cx<T> (&A)[S][C], int kb, int n, uint32_
   }
   if (lane == pl) used |= 1u << ps;
   const bool own = (w == kb);
+  // the look-ahead wave's chain (column k+1, pivot, publication) is what the
+  // next barrier waits for: it issues ahead of the other wave on its SIMD
+  const bool la = (w == kbn && k + 1 < n);
+  if (la) __builtin_amdgcn_s_setprio(2);
   {
     cx<T> v1[1];
     gj_row_chunk<T, S, C, JN, 1, -1, 0>(A, ps, pl, v1);
     gj_update_column<T, S, C, JN>(A, m, v1[0]);
   }
-  if (w == kbn && k + 1 < n)
+  if (la) {
     gj_select_pivot<T, NW, S, C, JN>(A, k + 1, n, used, colbuf, pivrow, flag);
+    __builtin_amdgcn_s_setprio(0);
+  }
   gj_update_chunks<T, S, C, J, JN, 0>(A, m, ps, pl, own);
 }
 

@@ -156,13 +156,17 @@ __device__ __forceinline__ void pgj_step(cx<double> (&A)[RS][RC], int kb, int ns
   }
   if (lane == pl) used |= 1u << ps;
   const bool own = (w == kb);
+  const bool la = (w == kbn && k + 1 < nsteps);  // the look-ahead wave issues first
+  if (la) __builtin_amdgcn_s_setprio(2);
   {
     cx<double> v1[1];
     gj_row_chunk<double, RS, RC, JN, 1, -1, 0>(A, ps, pl, v1);
     gj_update_column<double, RS, RC, JN>(A, m, v1[0]);
   }
-  if (w == kbn && k + 1 < nsteps)
+  if (la) {
     pgj_select_pivot<RS, RC, JN>(A, k + 1, n, used, colbuf, pivrow, flag);
+    __builtin_amdgcn_s_setprio(0);
+  }
   gj_update_chunks<double, RS, RC, J, JN, 0>(A, m, ps, pl, own);
 }
 
