@@ -594,7 +594,7 @@ def row_batched(args):
         out[prec] = dict(wall=wall, ev=ev, err=err, tiles=tiles, T=Ts)
         _say(f"batched {prec}: {wall / args.steps:.3f} s per step")
     dmix = None
-    if "mixed" in out:
+    if "mixed" in out and "fp64" in out:
         dmix = max(float(np.abs(a - b).max()) for a, b in zip(out["mixed"]["T"], out["fp64"]["T"]))
         out["mixed"]["vs64"] = dmix
     if "fp64" in out:
